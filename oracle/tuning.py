@@ -1,0 +1,78 @@
+"""Oracle for the tuner's statistics — TEST INFRASTRUCTURE ONLY.
+
+Plain Python/numpy definitions, each citing where the paper defines it, used
+by the tests to check the statistics the C++ tuner and serving loop report.
+
+* Tuning impact (Section 4, "Tuning impact"; Table 3 caption): performance of
+  the global optimum divided by the median performance over the search space.
+* Application efficiency e_i(x) (Section 4, Eq. 3): P_i(x) / max_x P_i(x).
+* Performance portability PP(x, H) (Section 4, Eq. 2): the harmonic mean of
+  e_i(x) over the set H (|H| / sum 1/e_i); 0 when any e_i is 0.
+* Medians follow the numpy convention (mean of the two middle values for an
+  even count); the paper does not fix one.
+* Winner selection (the paper is silent): the lowest time wins; times within
+  ``rel_tie`` of the lowest count as ties, and a tie goes to the
+  lexicographically smallest configuration tuple.
+* Latency percentiles (the paper has none; the serving loop reports them):
+  nearest rank, the ceil(p/100 * n)-th smallest value.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def median(values) -> float:
+    v = np.sort(np.asarray(values, dtype=np.float64))
+    n = v.size
+    if n == 0:
+        raise ValueError("median of an empty set")
+    if n % 2:
+        return float(v[n // 2])
+    return float(0.5 * (v[n // 2 - 1] + v[n // 2]))
+
+
+def tuning_impact(perf) -> float:
+    """max(perf) / median(perf), perf as throughput (higher is better)."""
+    return float(np.max(perf)) / median(perf)
+
+
+def gflops(out_h: int, out_w: int, fh: int, fw: int, seconds: float) -> float:
+    """Convolution throughput: 2*H*W*fh*fw floating-point operations per run."""
+    return 2.0 * out_h * out_w * fh * fw / seconds / 1e9
+
+
+def pick_winner(times: dict, rel_tie: float = 0.005):
+    """``times`` maps configuration tuples to seconds; returns the winner."""
+    best = min(times.values())
+    tied = [c for c, t in times.items() if t <= best * (1.0 + rel_tie)]
+    return min(tied)
+
+
+def top_k(times: dict, k: int = 5):
+    """The ``k`` fastest configurations, fastest first (ties by tuple order)."""
+    return sorted(times, key=lambda c: (times[c], c))[:k]
+
+
+def efficiency(perf_x: float, perf_all) -> float:
+    """Eq. 3: P_i(x) / max over the space of P_i."""
+    return float(perf_x) / float(np.max(perf_all))
+
+
+def performance_portability(effs) -> float:
+    """Eq. 2: |H| / sum_i 1/e_i (0 if any e_i is 0)."""
+    effs = [float(e) for e in effs]
+    if not effs:
+        raise ValueError("empty device/shape set")
+    if any(e <= 0.0 for e in effs):
+        return 0.0
+    return len(effs) / sum(1.0 / e for e in effs)
+
+
+def percentile_nearest_rank(values, p: float) -> float:
+    v = np.sort(np.asarray(values, dtype=np.float64))
+    if v.size == 0:
+        raise ValueError("percentile of an empty set")
+    rank = max(1, math.ceil(p / 100.0 * v.size))
+    return float(v[rank - 1])
