@@ -1,0 +1,215 @@
+/*
+ * conv2d.h — C ABI of the MI355X (gfx950) auto-tuned direct 2D convolution.
+ *
+ * The operation (the convolution benchmark of the paper's Section 5, whose
+ * tunable parameters are Table 1; the paper names the kernel, the formula
+ * below is the valid cross-correlation that kernel computes):
+ *
+ *     out[y][x] = sum_{i<fh} sum_{j<fw} in[y+i][x+j] * f[i][j]
+ *
+ * for 0 <= y < out_h, 0 <= x < out_w. `in` is (out_h+fh-1) x (out_w+fw-1),
+ * `f` is fh x fw and `out` is out_h x out_w, all dense row-major FP32 (row
+ * pitch = row width). No filter flip, no implicit padding: the caller's input
+ * already holds the halo.
+ *
+ * Conventions for every entry point:
+ *  - Return 0 (CONV2D_OK) on success or a negative conv2d_status; nothing
+ *    throws across this boundary. conv2d_last_error() returns a thread-local
+ *    message for the last non-zero return on the calling thread.
+ *  - d_* pointers are device memory on the current HIP device, owned by the
+ *    caller; the library never frees them. They must be 4-byte aligned, and
+ *    `d_out` must not overlap `d_in` or `d_filter`. Pointers are checked
+ *    against their allocation (hipMemGetAddressRange) before any launch, so a
+ *    buffer that is too small is an error (CONV2D_EINVAL), not a fault.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *    null stream). The caller keeps the buffers alive until the stream has
+ *    passed the call.
+ *  - Every configuration accumulates each output in one FP32 register, with
+ *    fused multiply-add, taps in i-ascending then j-ascending order, starting
+ *    from 0. Results are therefore bitwise identical across configurations,
+ *    batch and serving paths, and the reference kernel.
+ *  - Filter sizes are limited to 1..63 per axis; out_h, out_w >= 1.
+ */
+#ifndef CONV2D_H
+#define CONV2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum conv2d_status {
+    CONV2D_OK = 0,
+    CONV2D_EINVAL = -1,    /* bad argument, shape, config or pointer */
+    CONV2D_ENOMEM = -2,    /* device or host allocation failed */
+    CONV2D_ECOMPILE = -3,  /* hiprtc rejected the configuration */
+    CONV2D_ELAUNCH = -4,   /* the kernel launch failed */
+    CONV2D_ENOTUNED = -5,  /* no tuned winner for this shape and none forced */
+    CONV2D_EVERIFY = -6,   /* a configuration's output differed from the reference */
+    CONV2D_EHIP = -7,      /* another HIP runtime error (message in last_error) */
+    CONV2D_EBUSY = -8      /* serving: request cannot be admitted now */
+} conv2d_status;
+
+/* One point of the search space (the MI355X version of the paper's Table 1
+ * convolution parameters). */
+typedef struct conv2d_config {
+    int block_x;          /* threads along x: 16, 32, 64, 128 (block_size_x) */
+    int block_y;          /* threads along y: 1, 2, 4, 8, 16 (block_size_y) */
+    int tile_x;           /* outputs per thread along x: 1, 2, 4, 8 (tile_size_x) */
+    int tile_y;           /* outputs per thread along y: 1, 2, 4, 8 (tile_size_y) */
+    int use_lds;          /* 1: stage the workgroup's input halo in LDS (use_shmem) */
+    int filter_in_const;  /* 1: filter in a __constant__ array, 0: const global pointer
+                             (the analogue of read_only) */
+    int unroll;           /* input-row loop unroll: 1, 2, 4, or 0 = full
+                             (the paper's tunable partial unroll, Section 3) */
+} conv2d_config;
+
+typedef struct conv2d_shape {
+    int out_h, out_w;     /* output rows and columns */
+    int filt_h, filt_w;   /* filter rows and columns (input is (out_h+filt_h-1) x (out_w+filt_w-1)) */
+} conv2d_shape;
+
+typedef struct conv2d_plan_s *conv2d_plan_t;
+typedef struct conv2d_batch_s *conv2d_batch_t;
+
+/* ---------------------------------------------------------------- host only
+ * These never touch a GPU and can be called on a machine without one. */
+
+/* Library version (major*10000 + minor*100 + patch). */
+int conv2d_version(void);
+
+/* Thread-local text of the last non-zero return on this thread ("" if none). */
+const char *conv2d_last_error(void);
+
+/* The untuned default configuration: the textbook 16x16-thread tiled kernel,
+ * one output per thread, LDS halo, filter in constant memory, unroll 1. */
+void conv2d_default_config(conv2d_config *cfg);
+
+/* LDS bytes a configuration needs for a filter size (0 when use_lds = 0). */
+int conv2d_lds_bytes(int filt_h, int filt_w, const conv2d_config *cfg);
+
+/* Legality of a configuration for a shape: axis values in range,
+ * block_x*block_y <= 1024, LDS bytes <= lds_limit (pass 0 for the gfx950
+ * value, 163840). Returns CONV2D_OK or CONV2D_EINVAL with a reason. */
+int conv2d_config_check(conv2d_shape s, const conv2d_config *cfg, int lds_limit);
+
+/* Enumerates the restricted search space for a shape in axis order
+ * (block_x, block_y, tile_x, tile_y, use_lds, filter_in_const), with the given
+ * unroll for every point; writes up to `cap` configurations to `out` (may be
+ * NULL) and returns the number of legal points (or a negative status).
+ * With lds_limit < 0 only the thread-count restriction is applied. */
+int conv2d_space(conv2d_shape s, int unroll, int lds_limit, conv2d_config *out, int cap);
+
+/* Compiles one configuration for gfx950 with hiprtc into the code-object
+ * cache (no GPU needed). vec_in/vec_out are the alignment classes 1, 2 or 4.
+ * Writes the cache file path to path_out (if non-NULL, cap bytes).
+ * Returns CONV2D_OK or CONV2D_ECOMPILE (log in last_error). */
+int conv2d_compile(conv2d_shape s, const conv2d_config *cfg, int vec_in, int vec_out,
+                   char *path_out, int path_cap);
+
+/* Launch geometry of a configuration: tiles along x and y for one band of
+ * rows (the kernel covers the output with tiles of
+ * (block_x*tile_x) x (block_y*tile_y), one workgroup per tile). */
+int conv2d_geometry(conv2d_shape s, const conv2d_config *cfg, int *tiles_x, int *tiles_y,
+                    int *threads_per_block);
+
+/* Winners cache (JSON lines; the last line for a key wins). Key: GPU arch,
+ * shape, and the kernel source hash. arch may be NULL for the current
+ * device's arch. lookup returns CONV2D_ENOTUNED when absent. */
+int conv2d_cache_lookup(const char *path, const char *arch, conv2d_shape s,
+                        conv2d_config *cfg, double *ms);
+int conv2d_cache_store(const char *path, const char *arch, conv2d_shape s,
+                       const conv2d_config *cfg, double ms);
+
+/* ---------------------------------------------------------------- plain path */
+
+/* Creates a plan for one shape on the current device. cfg = NULL takes the
+ * tuned winner from the winners cache (env CONV2D_WINNERS, else the
+ * tuned/winners.jsonl file beside this library), else the default
+ * configuration; the environment variable CONV2D_FORCE_CONFIG
+ * ("bx,by,tx,ty,lds,const,unroll") overrides both. Compiles (or loads from the
+ * code-object cache) and loads the module. The plan owns the module. */
+int conv2d_plan(conv2d_plan_t *plan, conv2d_shape s, const conv2d_config *cfg);
+
+/* The configuration a plan uses, and whether it came from the winners cache
+ * (*tuned = 1), was forced or given (2), or is the default (0). */
+int conv2d_plan_config(conv2d_plan_t plan, conv2d_config *cfg, int *tuned);
+
+/* Enqueues one convolution on `stream`. With filter_in_const = 1 the filter is
+ * first copied (device to device, on the same stream) into the module's
+ * constant array: such a plan must not run concurrently on two streams. */
+int conv2d_run(conv2d_plan_t plan, const float *d_in, const float *d_filter, float *d_out,
+               void *stream);
+
+void conv2d_destroy(conv2d_plan_t plan);
+
+/* Plain reference kernel: one thread per output, runtime filter size, the
+ * same accumulation order as every configuration. Used by the tuner to verify
+ * each configuration bitwise. */
+int conv2d_reference(conv2d_shape s, const float *d_in, const float *d_filter, float *d_out,
+                     void *stream);
+
+/* Fills n floats of device memory with the seeded uniform values of the
+ * splitmix64 recipe (hash element start+k of `seed`, mapped to
+ * (top24 - 2^23) * 2^-23), on `stream`. */
+int conv2d_fill_uniform(float *d_out, size_t n, uint64_t seed, uint64_t start, void *stream);
+
+/* ---------------------------------------------------------------- tuner */
+
+typedef struct conv2d_tune_opts {
+    const char *winners_path;  /* winners cache to update (NULL: none) */
+    const char *results_path;  /* per-configuration results, JSON lines, resumable (NULL: none) */
+    int warmup;                /* untimed launches per configuration (default 2) */
+    int reps;                  /* timed launches per configuration (default 20) */
+    int retime_reps;           /* re-timing launches for the top 5 (default 50) */
+    int flush_mall;            /* 1: overwrite a 512 MiB buffer before each timed launch */
+    int threads;               /* host compile threads (0: all cores, at most 16) */
+    int unroll;                /* unroll value for every point (default 1) */
+    int max_configs;           /* 0: whole space, else the first N legal points (tests) */
+    double tie_rel;            /* relative tie window for the winner (default 0.005) */
+} conv2d_tune_opts;
+
+typedef struct conv2d_tune_result {
+    conv2d_config best;        /* the winner */
+    double best_ms;            /* its median time after re-timing */
+    double default_ms;         /* median time of the default configuration (0 if not timed) */
+    double median_ms;          /* time of the median-throughput configuration */
+    double best_gflops, median_gflops, default_gflops;
+    double impact;             /* best / median throughput (the paper's tuning impact) */
+    int n_space;               /* points in the restricted product */
+    int n_illegal;             /* rejected by the shape-dependent restrictions (LDS) */
+    int n_compile_fail, n_launch_fail, n_verify_fail;
+    int n_timed;               /* configurations timed successfully */
+    int n_resumed;             /* results reused from results_path */
+    int default_rank;          /* 1-based rank of the default among timed configs (0: n/a) */
+    conv2d_config top[5];      /* fastest five, fastest first */
+    double top_ms[5];
+    double compile_s, measure_s; /* wall time of the compile and measure phases */
+} conv2d_tune_result;
+
+/* Defaults for every option. */
+void conv2d_tune_defaults(conv2d_tune_opts *opts);
+
+/* Compiles every legal point (in parallel on host threads), then for each:
+ * launches it once and checks its output bitwise against the reference kernel,
+ * times it with HIP events (median of `reps`), and records it. The top five
+ * are re-timed, the winner chosen (lowest time; ties within tie_rel go to the
+ * smallest configuration tuple) and stored in the winners cache. Inputs are
+ * the seeded uniform recipe (input seed 1, filter seed 2), on device. */
+int conv2d_tune(conv2d_shape s, const conv2d_tune_opts *opts, conv2d_tune_result *res);
+
+/* The same search with a caller-supplied cost instead of the GPU (a fake
+ * backend for host tests): cost(cfg, user) returns a time in ms, or a
+ * negative status to mark a compile (-3), launch (-4) or verify (-6)
+ * failure. */
+typedef double (*conv2d_cost_fn)(const conv2d_config *cfg, void *user);
+int conv2d_tune_synthetic(conv2d_shape s, conv2d_cost_fn cost, void *user,
+                          const conv2d_tune_opts *opts, conv2d_tune_result *res);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONV2D_H */

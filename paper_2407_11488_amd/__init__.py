@@ -1,0 +1,21 @@
+"""Auto-tuned FP32 direct 2D convolution for MI355X (gfx950).
+
+``out[y][x] = sum_{i,j} in[y+i][x+j] * f[i][j]`` (valid cross-correlation),
+hand-written HIP behind a C ABI (``include/conv2d.h``); this package is the
+thin binding. PyTorch is used only for device memory and streams.
+
+    import torch, paper_2407_11488_amd as C
+    plan = C.Plan(4096, 4096, 17, 17)            # tuned winner if cached
+    out = plan(inp_cuda, filt_cuda)               # enqueued on the current stream
+"""
+from __future__ import annotations
+
+from ._binding import (CONV2D_EBUSY, CONV2D_ECOMPILE, CONV2D_EHIP, CONV2D_EINVAL, CONV2D_ELAUNCH,  # noqa: F401
+                       CONV2D_ENOMEM, CONV2D_ENOTUNED, CONV2D_EVERIFY, CONV2D_OK, LIB_PATH, Config,
+                       Conv2dError, Shape, TuneOpts, TuneResult, config, conv2d_cache_lookup,
+                       conv2d_cache_store, conv2d_compile, conv2d_config_check, conv2d_default_config,
+                       conv2d_destroy, conv2d_fill_uniform, conv2d_geometry, conv2d_last_error,
+                       conv2d_lds_bytes, conv2d_plan, conv2d_plan_config, conv2d_reference, conv2d_run,
+                       conv2d_space, conv2d_tune, conv2d_tune_defaults, conv2d_tune_synthetic,
+                       conv2d_version, lib, shape)
+from .api import Plan, conv2d, reference  # noqa: F401

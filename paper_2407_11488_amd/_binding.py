@@ -1,0 +1,257 @@
+"""ctypes binding of libconv2d.so: the C entry points under the same names.
+
+Argument marshalling only; every step of the computation runs in the HIP
+library. Import fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libconv2d.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_11488_amd.build` "
+                      "(there is no CPU fallback)")
+
+# PyTorch ships its own HIP runtime. Loading it first makes the library's
+# libamdhip64.so.7 / libhiprtc.so.7 dependencies resolve to those already
+# loaded copies, so that device memory allocated by torch and by this library
+# belongs to one runtime. (Loaded the other way round, torch would map a
+# second runtime beside the system one.)
+try:
+    import torch  # noqa: F401
+except ImportError:  # standalone use: the system ROCm runtime
+    torch = None
+
+lib = ctypes.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    try:
+        with open("/proc/self/maps") as fh:
+            return sorted({ln.split()[-1] for ln in fh if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are mapped in this process (" + ", ".join(_hip_runtimes()) +
+                      "); import torch before loading libconv2d.so")
+
+c_int, c_double, c_void_p, c_char_p, c_size_t, c_uint64 = (
+    ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_uint64)
+
+STATUS = {0: "CONV2D_OK", -1: "CONV2D_EINVAL", -2: "CONV2D_ENOMEM", -3: "CONV2D_ECOMPILE",
+          -4: "CONV2D_ELAUNCH", -5: "CONV2D_ENOTUNED", -6: "CONV2D_EVERIFY", -7: "CONV2D_EHIP",
+          -8: "CONV2D_EBUSY"}
+CONV2D_OK, CONV2D_EINVAL, CONV2D_ENOMEM, CONV2D_ECOMPILE = 0, -1, -2, -3
+CONV2D_ELAUNCH, CONV2D_ENOTUNED, CONV2D_EVERIFY, CONV2D_EHIP, CONV2D_EBUSY = -4, -5, -6, -7, -8
+
+
+class Conv2dError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib.conv2d_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("out_h", c_int), ("out_w", c_int), ("filt_h", c_int), ("filt_w", c_int)]
+
+    def tuple(self):
+        return (self.out_h, self.out_w, self.filt_h, self.filt_w)
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("block_x", c_int), ("block_y", c_int), ("tile_x", c_int), ("tile_y", c_int),
+                ("use_lds", c_int), ("filter_in_const", c_int), ("unroll", c_int)]
+
+    def tuple(self):
+        return tuple(getattr(self, f) for f, _ in self._fields_)
+
+    def __repr__(self):
+        return "Config(" + ",".join(str(v) for v in self.tuple()) + ")"
+
+
+class TuneOpts(ctypes.Structure):
+    _fields_ = [("winners_path", c_char_p), ("results_path", c_char_p), ("warmup", c_int), ("reps", c_int),
+                ("retime_reps", c_int), ("flush_mall", c_int), ("threads", c_int), ("unroll", c_int),
+                ("max_configs", c_int), ("tie_rel", c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", Config), ("best_ms", c_double), ("default_ms", c_double), ("median_ms", c_double),
+                ("best_gflops", c_double), ("median_gflops", c_double), ("default_gflops", c_double),
+                ("impact", c_double), ("n_space", c_int), ("n_illegal", c_int), ("n_compile_fail", c_int),
+                ("n_launch_fail", c_int), ("n_verify_fail", c_int), ("n_timed", c_int), ("n_resumed", c_int),
+                ("default_rank", c_int), ("top", Config * 5), ("top_ms", c_double * 5),
+                ("compile_s", c_double), ("measure_s", c_double)]
+
+
+COST_FN = ctypes.CFUNCTYPE(c_double, ctypes.POINTER(Config), c_void_p)
+P = ctypes.POINTER
+
+_SIGS = {
+    "conv2d_version": (c_int, []),
+    "conv2d_last_error": (c_char_p, []),
+    "conv2d_default_config": (None, [P(Config)]),
+    "conv2d_lds_bytes": (c_int, [c_int, c_int, P(Config)]),
+    "conv2d_config_check": (c_int, [Shape, P(Config), c_int]),
+    "conv2d_space": (c_int, [Shape, c_int, c_int, P(Config), c_int]),
+    "conv2d_compile": (c_int, [Shape, P(Config), c_int, c_int, c_char_p, c_int]),
+    "conv2d_geometry": (c_int, [Shape, P(Config), P(c_int), P(c_int), P(c_int)]),
+    "conv2d_cache_lookup": (c_int, [c_char_p, c_char_p, Shape, P(Config), P(c_double)]),
+    "conv2d_cache_store": (c_int, [c_char_p, c_char_p, Shape, P(Config), c_double]),
+    "conv2d_plan": (c_int, [P(c_void_p), Shape, P(Config)]),
+    "conv2d_plan_config": (c_int, [c_void_p, P(Config), P(c_int)]),
+    "conv2d_run": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "conv2d_destroy": (None, [c_void_p]),
+    "conv2d_reference": (c_int, [Shape, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "conv2d_fill_uniform": (c_int, [c_void_p, c_size_t, c_uint64, c_uint64, c_void_p]),
+    "conv2d_tune_defaults": (None, [P(TuneOpts)]),
+    "conv2d_tune": (c_int, [Shape, P(TuneOpts), P(TuneResult)]),
+    "conv2d_tune_synthetic": (c_int, [Shape, COST_FN, c_void_p, P(TuneOpts), P(TuneResult)]),
+}
+
+
+def _bind():
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+_bind()
+
+
+def check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise Conv2dError(rc, where)
+    return rc
+
+
+def shape(out_h, out_w, filt_h, filt_w) -> Shape:
+    return Shape(int(out_h), int(out_w), int(filt_h), int(filt_w))
+
+
+def config(*vals) -> Config:
+    if len(vals) == 1 and isinstance(vals[0], (tuple, list, Config)):
+        vals = tuple(vals[0].tuple() if isinstance(vals[0], Config) else vals[0])
+    if len(vals) == 6:
+        vals = (*vals, 1)
+    return Config(*[int(v) for v in vals])
+
+
+# ---------------------------------------------------------------- entry points (same names)
+
+def conv2d_version() -> int:
+    return lib.conv2d_version()
+
+
+def conv2d_last_error() -> str:
+    return lib.conv2d_last_error().decode(errors="replace")
+
+
+def conv2d_default_config() -> Config:
+    c = Config()
+    lib.conv2d_default_config(ctypes.byref(c))
+    return c
+
+
+def conv2d_lds_bytes(filt_h: int, filt_w: int, cfg) -> int:
+    return check(lib.conv2d_lds_bytes(filt_h, filt_w, ctypes.byref(config(cfg))), "conv2d_lds_bytes")
+
+
+def conv2d_config_check(s: Shape, cfg, lds_limit: int = 0) -> int:
+    """Returns 0 when legal, else the negative status (no exception)."""
+    return lib.conv2d_config_check(s, ctypes.byref(config(cfg)), lds_limit)
+
+
+def conv2d_space(s: Shape, unroll: int = 1, lds_limit: int = 0):
+    n = check(lib.conv2d_space(s, unroll, lds_limit, None, 0), "conv2d_space")
+    arr = (Config * max(n, 1))()
+    lib.conv2d_space(s, unroll, lds_limit, arr, n)
+    return [arr[i].tuple() for i in range(n)]
+
+
+def conv2d_compile(s: Shape, cfg, vec_in: int = 4, vec_out: int = 4) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    check(lib.conv2d_compile(s, ctypes.byref(config(cfg)), vec_in, vec_out, buf, 4096), "conv2d_compile")
+    return buf.value.decode()
+
+
+def conv2d_geometry(s: Shape, cfg):
+    tx, ty, nt = c_int(), c_int(), c_int()
+    check(lib.conv2d_geometry(s, ctypes.byref(config(cfg)), ctypes.byref(tx), ctypes.byref(ty),
+                              ctypes.byref(nt)), "conv2d_geometry")
+    return tx.value, ty.value, nt.value
+
+
+def _b(s):
+    return None if s is None else (s.encode() if isinstance(s, str) else s)
+
+
+def conv2d_cache_lookup(path, arch, s: Shape):
+    c, ms = Config(), c_double()
+    rc = lib.conv2d_cache_lookup(_b(path), _b(arch), s, ctypes.byref(c), ctypes.byref(ms))
+    if rc == CONV2D_ENOTUNED:
+        return None
+    check(rc, "conv2d_cache_lookup")
+    return c, ms.value
+
+
+def conv2d_cache_store(path, arch, s: Shape, cfg, ms: float) -> None:
+    check(lib.conv2d_cache_store(_b(path), _b(arch), s, ctypes.byref(config(cfg)), ms), "conv2d_cache_store")
+
+
+def conv2d_plan(s: Shape, cfg=None) -> int:
+    h = c_void_p()
+    check(lib.conv2d_plan(ctypes.byref(h), s, None if cfg is None else ctypes.byref(config(cfg))), "conv2d_plan")
+    return h.value
+
+
+def conv2d_plan_config(plan: int):
+    c, src = Config(), c_int()
+    check(lib.conv2d_plan_config(plan, ctypes.byref(c), ctypes.byref(src)), "conv2d_plan_config")
+    return c, src.value
+
+
+def conv2d_run(plan: int, d_in: int, d_filter: int, d_out: int, stream: int = 0) -> None:
+    check(lib.conv2d_run(plan, d_in, d_filter, d_out, stream), "conv2d_run")
+
+
+def conv2d_destroy(plan: int) -> None:
+    lib.conv2d_destroy(plan)
+
+
+def conv2d_reference(s: Shape, d_in: int, d_filter: int, d_out: int, stream: int = 0) -> None:
+    check(lib.conv2d_reference(s, d_in, d_filter, d_out, stream), "conv2d_reference")
+
+
+def conv2d_fill_uniform(d_out: int, n: int, seed: int, start: int = 0, stream: int = 0) -> None:
+    check(lib.conv2d_fill_uniform(d_out, n, seed, start, stream), "conv2d_fill_uniform")
+
+
+def conv2d_tune_defaults() -> TuneOpts:
+    o = TuneOpts()
+    lib.conv2d_tune_defaults(ctypes.byref(o))
+    return o
+
+
+def conv2d_tune(s: Shape, opts: TuneOpts | None = None) -> TuneResult:
+    r = TuneResult()
+    check(lib.conv2d_tune(s, None if opts is None else ctypes.byref(opts), ctypes.byref(r)), "conv2d_tune")
+    return r
+
+
+def conv2d_tune_synthetic(s: Shape, cost, opts: TuneOpts | None = None) -> TuneResult:
+    """``cost(config_tuple) -> ms`` (or a negative status) replaces the GPU."""
+    def _cb(cp, _user):
+        return float(cost(cp.contents.tuple()))
+    cb = COST_FN(_cb)
+    r = TuneResult()
+    check(lib.conv2d_tune_synthetic(s, cb, None, None if opts is None else ctypes.byref(opts),
+                                    ctypes.byref(r)), "conv2d_tune_synthetic")
+    return r

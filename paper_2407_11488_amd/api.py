@@ -1,0 +1,86 @@
+"""Tensor-level helpers over the C entry points (PyTorch supplies device memory
+and the current stream; all computation is in the HIP library)."""
+from __future__ import annotations
+
+from . import _binding as B
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_tensor(t, name, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous float32")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _stream(stream):
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+class Plan:
+    """A compiled configuration for one (out_h, out_w, filt_h, filt_w) shape."""
+
+    def __init__(self, out_h, out_w, filt_h, filt_w, config=None):
+        self.shape = B.shape(out_h, out_w, filt_h, filt_w)
+        self.handle = B.conv2d_plan(self.shape, config)
+        cfg, src = B.conv2d_plan_config(self.handle)
+        self.config = cfg.tuple()
+        self.source = {0: "default", 1: "tuned", 2: "given"}.get(src, str(src))
+
+    def __call__(self, inp, filt, out=None, stream=None):
+        torch = _torch()
+        H, W, fh, fw = self.shape.tuple()
+        _check_tensor(inp, "inp", (H + fh - 1, W + fw - 1))
+        _check_tensor(filt, "filt", (fh, fw))
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=inp.device)
+        _check_tensor(out, "out", (H, W))
+        B.conv2d_run(self.handle, inp.data_ptr(), filt.data_ptr(), out.data_ptr(), _stream(stream))
+        return out
+
+    def close(self):
+        if self.handle:
+            B.conv2d_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_plans: dict = {}
+
+
+def conv2d(inp, filt, config=None, out=None, stream=None):
+    """One convolution; plans are cached per (shape, config)."""
+    fh, fw = filt.shape
+    H, W = inp.shape[0] - fh + 1, inp.shape[1] - fw + 1
+    key = (H, W, fh, fw, None if config is None else tuple(B.config(config).tuple()))
+    plan = _plans.get(key)
+    if plan is None:
+        plan = _plans[key] = Plan(H, W, fh, fw, config)
+    return plan(inp, filt, out=out, stream=stream)
+
+
+def reference(inp, filt, out=None, stream=None):
+    """The library's plain reference kernel (one thread per output)."""
+    torch = _torch()
+    fh, fw = filt.shape
+    H, W = inp.shape[0] - fh + 1, inp.shape[1] - fw + 1
+    _check_tensor(inp, "inp")
+    _check_tensor(filt, "filt")
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=inp.device)
+    B.conv2d_reference(B.shape(H, W, fh, fw), inp.data_ptr(), filt.data_ptr(), out.data_ptr(), _stream(stream))
+    return out

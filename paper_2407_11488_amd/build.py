@@ -1,0 +1,97 @@
+"""Builds libconv2d.so in-tree for gfx950.
+
+Host sources (*.cpp) are compiled with amdclang++ as plain C++ against the HIP
+headers; device sources (*.hip) with hipcc for gfx950. Packed FP32
+instructions are disabled in every device compilation. Run:
+
+    python -m paper_2407_11488_amd.build
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(ROOT, "_build", "conv2d")
+LIB = os.path.join(PKG, "libconv2d.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+ARCH = os.environ.get("CONV2D_BUILD_ARCH", "gfx950")
+
+HIPCC = os.path.join(ROCM, "bin", "hipcc")
+CXX = os.path.join(ROCM, "llvm", "bin", "clang++")
+NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+COMMON = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",
+          f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
+
+
+def _sources():
+    cpp = sorted(f for f in os.listdir(CSRC) if f.endswith(".cpp"))
+    hip = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip") and f != "conv2d_direct.hip")
+    return cpp, hip
+
+
+def _compile(src: str) -> str:
+    obj = os.path.join(BUILD, src + ".o")
+    path = os.path.join(CSRC, src)
+    if src.endswith(".cpp"):
+        cmd = [CXX, "-x", "c++", *COMMON, "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-c", path, "-o", obj]
+    else:
+        cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, *NO_PACKED_FP32, "-c", path, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def _check_direct_kernel():
+    """Compiles the run-time-compiled kernel source through the library's own
+    hiprtc path (no GPU needed) for the default and a register-tiled
+    configuration, so that an error in the kernel source fails the build."""
+    import ctypes
+
+    class Shape(ctypes.Structure):
+        _fields_ = [(n, ctypes.c_int) for n in ("out_h", "out_w", "filt_h", "filt_w")]
+
+    class Config(ctypes.Structure):
+        _fields_ = [(n, ctypes.c_int) for n in ("block_x", "block_y", "tile_x", "tile_y", "use_lds",
+                                                 "filter_in_const", "unroll")]
+
+    lib = ctypes.CDLL(LIB)
+    lib.conv2d_last_error.restype = ctypes.c_char_p
+    for cfg, vin, vout in (((16, 16, 1, 1, 1, 1, 1), 4, 4), ((64, 1, 8, 8, 0, 0, 1), 1, 2)):
+        rc = lib.conv2d_compile(Shape(64, 64, 17, 17), ctypes.byref(Config(*cfg)), vin, vout, None, 0)
+        if rc != 0:
+            raise RuntimeError(f"kernel source check failed for {cfg}: {lib.conv2d_last_error().decode()}")
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    cpp, hip = _sources()
+    jobs = min(16, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(_compile, cpp + hip))
+    tmp = LIB + f".tmp{os.getpid()}"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
+           f"-L{ROCM}/lib", "-lhiprtc", "-lamdhip64", "-lpthread", "-ldl", f"-Wl,-rpath,{ROCM}/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    _check_direct_kernel()
+    if verbose:
+        print(f"built {LIB}")
+    return LIB
+
+
+def clean():
+    shutil.rmtree(BUILD, ignore_errors=True)
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,137 @@
+// Fixed kernels compiled into the library for gfx950: the plain reference
+// convolution the tuner verifies against, the seeded input generator, a
+// bitwise comparison, fills, and the last-level-cache flush used between
+// timed launches.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace conv2d {
+
+namespace {
+
+// One thread per output, runtime filter size. Same accumulation order as the
+// tunable kernel: acc starts at 0, fma over i ascending then j ascending.
+__global__ void __launch_bounds__(256)
+reference_kernel(const float* __restrict__ in, const float* __restrict__ f, float* __restrict__ out,
+                 int H, int W, int fh, int fw)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)H * W) return;
+    const int y = (int)(idx / W);
+    const int x = (int)(idx - (long long)y * W);
+    const long long P = (long long)W + fw - 1;
+    float acc = 0.0f;
+    for (int i = 0; i < fh; ++i) {
+        const float* row = in + (long long)(y + i) * P + x;
+        for (int j = 0; j < fw; ++j)
+            acc = __builtin_fmaf(row[j], f[i * fw + j], acc);
+    }
+    out[idx] = acc;
+}
+
+// SplitMix64 output number `idx` of stream `seed` (Steele, Lea and Flood 2014).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long seed, unsigned long long idx)
+{
+    unsigned long long z = seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void fill_uniform_kernel(float* __restrict__ d, size_t n, unsigned long long seed,
+                                    unsigned long long start)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const unsigned long long z = splitmix64(seed, start + k);
+        const int k24 = (int)(z >> 40);
+        d[k] = (float)(k24 - (1 << 23)) * (1.0f / 8388608.0f);
+    }
+}
+
+__global__ void fill_value_kernel(float* __restrict__ d, size_t n, float v)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) d[k] = v;
+}
+
+__global__ void count_mismatch_kernel(const unsigned* __restrict__ a, const unsigned* __restrict__ b,
+                                      size_t n, unsigned* __restrict__ count)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    unsigned local = 0;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        local += (a[k] != b[k]) ? 1u : 0u;
+    // wave64 reduction through DPP-free shuffles
+    for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off, 64);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+}
+
+__global__ void flush_kernel(float4* __restrict__ d, size_t n4)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const float4 z = {0.f, 0.f, 0.f, 0.f};
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n4; k += stride) d[k] = z;
+}
+
+int grid_for(size_t n, int block)
+{
+    size_t g = (n + block - 1) / block;
+    if (g > 8192) g = 8192;  // grid-stride beyond 32 workgroups per CU
+    return g < 1 ? 1 : (int)g;
+}
+
+}  // namespace
+
+int launch_reference(const conv2d_shape& s, const float* d_in, const float* d_f, float* d_out,
+                     hipStream_t stream)
+{
+    const long long n = (long long)s.out_h * s.out_w;
+    const long long blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffll) return fail(CONV2D_EINVAL, "reference: image too large");
+    hipLaunchKernelGGL(reference_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, d_in, d_f,
+                       d_out, s.out_h, s.out_w, s.filt_h, s.filt_w);
+    CONV2D_HIP(hipGetLastError());
+    return CONV2D_OK;
+}
+
+int launch_fill_uniform(float* d, size_t n, uint64_t seed, uint64_t start, hipStream_t stream)
+{
+    if (n == 0) return CONV2D_OK;
+    hipLaunchKernelGGL(fill_uniform_kernel, dim3(grid_for(n, 256)), dim3(256), 0, stream, d, n,
+                       (unsigned long long)seed, (unsigned long long)start);
+    CONV2D_HIP(hipGetLastError());
+    return CONV2D_OK;
+}
+
+int launch_fill_value(float* d, size_t n, float v, hipStream_t stream)
+{
+    if (n == 0) return CONV2D_OK;
+    hipLaunchKernelGGL(fill_value_kernel, dim3(grid_for(n, 256)), dim3(256), 0, stream, d, n, v);
+    CONV2D_HIP(hipGetLastError());
+    return CONV2D_OK;
+}
+
+int launch_count_mismatch(const float* a, const float* b, size_t n, unsigned* d_count,
+                          hipStream_t stream)
+{
+    if (n == 0) return CONV2D_OK;
+    hipLaunchKernelGGL(count_mismatch_kernel, dim3(grid_for(n, 256)), dim3(256), 0, stream,
+                       reinterpret_cast<const unsigned*>(a), reinterpret_cast<const unsigned*>(b),
+                       n, d_count);
+    CONV2D_HIP(hipGetLastError());
+    return CONV2D_OK;
+}
+
+int launch_flush(float* d, size_t n, hipStream_t stream)
+{
+    const size_t n4 = n / 4;
+    if (n4 == 0) return CONV2D_OK;
+    hipLaunchKernelGGL(flush_kernel, dim3(grid_for(n4, 256)), dim3(256), 0, stream,
+                       reinterpret_cast<float4*>(d), n4);
+    CONV2D_HIP(hipGetLastError());
+    return CONV2D_OK;
+}
+
+}  // namespace conv2d

@@ -1,0 +1,255 @@
+// Direct 2D image convolution for gfx950 (CDNA4), one tunable configuration
+// per compilation. The host library compiles this file at run time with
+// hiprtc, once per (configuration, filter size, alignment class), the way the
+// paper's tuner compiles each point of its search space (Section 3; the
+// convolution's tunable parameters are Table 1).
+//
+// Computes, for 0 <= y < H, 0 <= x < W (valid cross-correlation, no flip):
+//     out[y][x] = sum_{i<FH} sum_{j<FW} in[y+i][x+j] * f[i][j]
+// with `in` (H+FH-1) x (W+FW-1), `f` FH x FW, `out` H x W, row-major FP32.
+//
+// Accumulation order is fixed for every configuration: one FP32 accumulator
+// per output, fused multiply-add, taps in i-ascending then j-ascending order.
+// Every configuration (and the batched kernel) therefore returns the same
+// bits for the same inputs.
+//
+// Compile-time parameters (-D):
+//   CONV_BX, CONV_BY   workgroup shape in threads (block_size_x / block_size_y)
+//   CONV_TX, CONV_TY   outputs per thread along x and y (tile_size_x / _y)
+//   CONV_USE_LDS       1: the workgroup stages its input halo tile in LDS
+//   CONV_FCONST        1: filter copied into this module's __constant__ array
+//                      0: filter read through a const __restrict__ pointer
+//   CONV_UNROLL        unroll of the input-row loop (0 = full)
+//   CONV_FH, CONV_FW   filter size
+//   CONV_VIN           input vector width 1/2/4 (row pitch and base aligned)
+//   CONV_VOUT          output vector width 1/2/4 (row pitch and base aligned)
+//
+// Design (MI355X):
+//  * Each thread owns a TY x TX register tile of outputs, contiguous in x.
+//    It walks the TY+FH-1 input rows its tile needs once each: a row window of
+//    TX+FW-1 values is loaded into VGPRs and feeds every output row that uses
+//    it (TY*TX*FW FMAs per window in the steady state). Filter taps are wave
+//    uniform and are read with scalar loads, so each FMA is
+//    v_fmac_f32 acc, s_tap, v_in.
+//  * Global reads use raw buffer loads: an out-of-range offset returns 0
+//    instead of faulting, so edge tiles need no clamping; outputs outside the
+//    image are simply not stored.
+//  * Workgroup ids are remapped so that each of the 8 XCDs (dispatched
+//    round-robin) receives one contiguous run of tiles, keeping vertically
+//    adjacent tiles, which share FH-1 input rows, in the same L2.
+
+#ifndef CONV_BX
+#error "CONV_BX must be defined"
+#endif
+
+#define NT (CONV_BX * CONV_BY)
+#define WIN (CONV_TX + CONV_FW - 1)
+#define NROWS (CONV_TY + CONV_FH - 1)
+
+#if CONV_UNROLL == 0
+#define ROW_UNROLL _Pragma("unroll")
+#elif CONV_UNROLL == 1
+#define ROW_UNROLL _Pragma("unroll 1")
+#elif CONV_UNROLL == 2
+#define ROW_UNROLL _Pragma("unroll 2")
+#elif CONV_UNROLL == 4
+#define ROW_UNROLL _Pragma("unroll 4")
+#else
+#define ROW_UNROLL _Pragma("unroll 8")
+#endif
+
+typedef unsigned int u32;
+typedef u32 u32x2 __attribute__((ext_vector_type(2)));
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#define GCD4(t) (((t) % 4 == 0) ? 4 : (((t) % 2 == 0) ? 2 : 1))
+#define MIN_(a, b) ((a) < (b) ? (a) : (b))
+
+// Vector width of a thread's window loads. The window starts at a multiple
+// of TX: from global memory it is aligned to min(gcd(TX, 4), VIN) elements,
+// from LDS (pitch a multiple of 4) to gcd(TX, 4). The register window is
+// padded to a whole number of those vectors.
+#if CONV_USE_LDS
+#define WVEC GCD4(CONV_TX)
+#else
+#define WVEC MIN_(GCD4(CONV_TX), CONV_VIN)
+#endif
+#define WIN_PAD (((WIN + WVEC - 1) / WVEC) * WVEC)
+// Output store width.
+#define SVEC MIN_(GCD4(CONV_TX), CONV_VOUT)
+
+#if CONV_FCONST
+__constant__ float conv_filter[CONV_FH * CONV_FW];
+#define TAP(i, j) conv_filter[(i) * CONV_FW + (j)]
+#else
+#define TAP(i, j) filt[(i) * CONV_FW + (j)]
+#endif
+
+static __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, u32 bytes)
+{
+    // Word 3 = 0x00020000: raw (untyped) dword access, the gfx9-family value.
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+
+// Loads N consecutive floats from byte offset `off` of the buffer into dst[0..N).
+// Whole vectors are bit-cast: bit-casting a single ext-vector element
+// (v.y, ...) is miscompiled by this clang into a read of element 0.
+template <int V, int N>
+static __device__ __forceinline__ void buffer_row(float* dst, __amdgpu_buffer_rsrc_t rs, u32 off)
+{
+#pragma unroll
+    for (int m = 0; m < N; m += V) {
+        if constexpr (V == 4) {
+            f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 4u * m), 0, 0));
+            dst[m + 0] = v.x;
+            dst[m + 1] = v.y;
+            dst[m + 2] = v.z;
+            dst[m + 3] = v.w;
+        } else if constexpr (V == 2) {
+            f32x2 v = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(off + 4u * m), 0, 0));
+            dst[m + 0] = v.x;
+            dst[m + 1] = v.y;
+        } else {
+            u32 v = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + 4u * m), 0, 0);
+            dst[m] = __builtin_bit_cast(float, v);
+        }
+    }
+}
+
+// Loads N consecutive floats from LDS (V-element aligned) into dst[0..N).
+template <int V, int N>
+static __device__ __forceinline__ void lds_row(float* dst, const float* src)
+{
+#pragma unroll
+    for (int m = 0; m < N; m += V) {
+        if constexpr (V == 4) {
+            f32x4 v = *(const f32x4*)(src + m);
+            dst[m + 0] = v.x; dst[m + 1] = v.y; dst[m + 2] = v.z; dst[m + 3] = v.w;
+        } else if constexpr (V == 2) {
+            f32x2 v = *(const f32x2*)(src + m);
+            dst[m + 0] = v.x; dst[m + 1] = v.y;
+        } else {
+            dst[m] = src[m];
+        }
+    }
+}
+
+// Workgroup id -> tile id: XCD x (= id mod 8) gets the contiguous tile range
+// [start(x), start(x) + count(x)); a bijection on [0, n_tiles).
+static __device__ __forceinline__ int xcd_remap(int id, int n_tiles)
+{
+    const int q = n_tiles >> 3, rem = n_tiles & 7;
+    const int xcd = id & 7, k = id >> 3;
+    return xcd * q + MIN_(xcd, rem) + k;
+}
+
+#if CONV_USE_LDS
+// Input halo tile of one workgroup, rows x pitch floats. The pitch is padded
+// to a multiple of 4 (aligned ds_read_b128) plus 4 when it would otherwise be
+// a multiple of 32 banks' worth, to spread the rows a wave reads over banks.
+#define LDS_ROWS (CONV_BY * CONV_TY + CONV_FH - 1)
+#define LDS_COLS (CONV_BX * CONV_TX + CONV_FW - 1)
+#define LDS_CHUNKS ((LDS_COLS + CONV_VIN - 1) / CONV_VIN)
+#define LDS_PITCH0 (((LDS_CHUNKS * CONV_VIN + 3) / 4) * 4)
+#define LDS_PITCH ((LDS_PITCH0 % 32 == 0) ? LDS_PITCH0 + 4 : LDS_PITCH0)
+#endif
+
+extern "C" __global__ void __launch_bounds__(NT)
+conv2d_direct(const float* __restrict__ in, const float* __restrict__ filt,
+              float* __restrict__ out, int H, int W, int tiles_x, int n_tiles, u32 in_bytes)
+{
+    const int t = xcd_remap((int)blockIdx.x, n_tiles);
+    const int tile_y = t / tiles_x;
+    const int tile_x = t - tile_y * tiles_x;
+    const int lx = (int)threadIdx.x % CONV_BX;
+    const int ly = (int)threadIdx.x / CONV_BX;
+    const int x0 = tile_x * (CONV_BX * CONV_TX) + lx * CONV_TX;
+    const int y0 = tile_y * (CONV_BY * CONV_TY) + ly * CONV_TY;
+    const u32 P = (u32)W + (CONV_FW - 1);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(in, in_bytes);
+
+#if CONV_USE_LDS
+    __shared__ __attribute__((aligned(16))) float tile[LDS_ROWS * LDS_PITCH];
+    {
+        const u32 gx0 = (u32)tile_x * (CONV_BX * CONV_TX);
+        const u32 gy0 = (u32)tile_y * (CONV_BY * CONV_TY);
+        for (int c = (int)threadIdx.x; c < LDS_ROWS * LDS_CHUNKS; c += NT) {
+            const int rr = c / LDS_CHUNKS;
+            const int cc = (c - rr * LDS_CHUNKS) * CONV_VIN;
+            float v[CONV_VIN];
+            buffer_row<CONV_VIN, CONV_VIN>(v, rs, ((gy0 + rr) * P + gx0 + cc) * 4u);
+#pragma unroll
+            for (int m = 0; m < CONV_VIN; ++m)
+                tile[rr * LDS_PITCH + cc + m] = v[m];
+        }
+    }
+    __syncthreads();
+    const float* lbase = tile + (ly * CONV_TY) * LDS_PITCH + lx * CONV_TX;
+#endif
+
+    if (x0 >= W || y0 >= H)
+        return;
+
+    float acc[CONV_TY][CONV_TX];
+#pragma unroll
+    for (int o = 0; o < CONV_TY; ++o)
+#pragma unroll
+        for (int k = 0; k < CONV_TX; ++k)
+            acc[o][k] = 0.0f;
+
+#if !CONV_USE_LDS
+    const u32 off0 = ((u32)y0 * P + (u32)x0) * 4u;
+#endif
+
+    ROW_UNROLL
+    for (int r = 0; r < NROWS; ++r) {
+        float w[WIN_PAD];
+#if CONV_USE_LDS
+        lds_row<WVEC, WIN_PAD>(w, lbase + r * LDS_PITCH);
+#else
+        buffer_row<WVEC, WIN_PAD>(w, rs, off0 + (u32)r * P * 4u);
+#endif
+#pragma unroll
+        for (int o = 0; o < CONV_TY; ++o) {
+            const int i = r - o;
+            if (i >= 0 && i < CONV_FH) {
+#pragma unroll
+                for (int j = 0; j < CONV_FW; ++j) {
+                    const float fv = TAP(i, j);
+#pragma unroll
+                    for (int k = 0; k < CONV_TX; ++k)
+                        acc[o][k] = __builtin_fmaf(w[k + j], fv, acc[o][k]);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int o = 0; o < CONV_TY; ++o) {
+        const int y = y0 + o;
+        if (y < H) {
+            float* orow = out + (size_t)y * (size_t)W + x0;
+            if (x0 + CONV_TX <= W) {
+#pragma unroll
+                for (int k = 0; k < CONV_TX; k += SVEC) {
+                    if constexpr (SVEC == 4) {
+                        f32x4 v = {acc[o][k], acc[o][k + 1], acc[o][k + 2], acc[o][k + 3]};
+                        __builtin_nontemporal_store(v, (f32x4*)(orow + k));
+                    } else if constexpr (SVEC == 2) {
+                        f32x2 v = {acc[o][k], acc[o][k + 1]};
+                        __builtin_nontemporal_store(v, (f32x2*)(orow + k));
+                    } else {
+                        __builtin_nontemporal_store(acc[o][k], orow + k);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < CONV_TX; ++k)
+                    if (x0 + k < W)
+                        orow[k] = acc[o][k];
+            }
+        }
+    }
+}

@@ -1,0 +1,129 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "conv2d.h"
+
+namespace conv2d {
+
+// ---------------------------------------------------------------- errors
+// Sets the thread-local last-error text and returns `status`.
+int fail(int status, const std::string& msg);
+void clear_error();
+const char* last_error_cstr();
+// Maps a HIP error to CONV2D_EHIP with its text (prefixed by `what`).
+int hip_fail(hipError_t e, const char* what);
+#define CONV2D_HIP(call)                                  \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return ::conv2d::hip_fail(e_, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------- misc
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull);
+uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull);
+std::string hex64(uint64_t v);
+std::string env_str(const char* name, const char* dflt = "");
+// Directory that holds this shared library.
+std::string library_dir();
+bool make_dirs(const std::string& path);
+bool write_file_atomic(const std::string& path, const void* data, size_t n);
+bool read_file(const std::string& path, std::vector<char>& out);
+double now_s();
+
+// ---------------------------------------------------------------- configs
+constexpr int kMaxFilter = 63;
+constexpr int kMaxThreads = 1024;
+constexpr int kLdsLimitGfx950 = 163840;
+bool config_axes_valid(const conv2d_config& c, std::string* why);
+std::string config_str(const conv2d_config& c);
+bool parse_config(const std::string& s, conv2d_config* c);
+// Tuple order used for tie-breaks: (bx, by, tx, ty, lds, const, unroll).
+bool config_less(const conv2d_config& a, const conv2d_config& b);
+bool config_equal(const conv2d_config& a, const conv2d_config& b);
+int lds_bytes(int fh, int fw, const conv2d_config& c);
+int shape_check(const conv2d_shape& s);
+
+// ---------------------------------------------------------------- JIT
+// Kernel source text of the tunable direct convolution (embedded at build).
+const std::string& direct_source();
+uint64_t direct_source_hash();
+// hiprtc options for one configuration (packed FP32 disabled).
+std::vector<std::string> direct_options(const conv2d_shape& s, const conv2d_config& c,
+                                        int vin, int vout, const std::string& arch);
+// Compile (or read from the disk cache) the code object for a configuration.
+// Returns CONV2D_OK or CONV2D_ECOMPILE. Thread safe.
+int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int vout,
+                   const std::string& arch, std::vector<char>* code, std::string* path);
+std::string code_cache_dir();
+
+// A loaded module with the direct kernel and its constant-filter symbol.
+struct Module {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    void* const_filter = nullptr;   // device address of conv_filter (FCONST=1)
+    size_t const_bytes = 0;
+};
+int load_module(const std::vector<char>& code, Module* m);
+void unload_module(Module* m);
+
+// ---------------------------------------------------------------- device
+struct DeviceInfo {
+    int device = -1;
+    std::string arch;       // e.g. "gfx950" (features stripped)
+    int cus = 0;
+    int lds_limit = 0;      // bytes per workgroup
+    int clock_khz = 0;
+};
+int current_device_info(DeviceInfo* info);
+// Checks that [p, p+bytes) lies inside one device allocation.
+int check_device_range(const void* p, size_t bytes, const char* name);
+
+// ---------------------------------------------------------------- launch
+struct Geometry {
+    int tiles_x = 0, tiles_y = 0, n_tiles = 0, threads = 0;
+};
+Geometry geometry(int out_h, int out_w, const conv2d_config& c);
+// Largest number of output rows per launch so that the input band stays below
+// 2^31 bytes (buffer offsets are 32-bit).
+int band_rows(const conv2d_shape& s);
+int vec_class(long long elems_per_row);
+// Launches the direct kernel of `m` over the whole shape (in bands) on stream.
+int launch_direct(const Module& m, const conv2d_shape& s, const conv2d_config& c,
+                  const float* d_in, const float* d_f, float* d_out, hipStream_t stream);
+
+// ---------------------------------------------------------------- aux kernels
+int launch_reference(const conv2d_shape& s, const float* d_in, const float* d_f, float* d_out,
+                     hipStream_t stream);
+int launch_fill_uniform(float* d, size_t n, uint64_t seed, uint64_t start, hipStream_t stream);
+int launch_fill_value(float* d, size_t n, float v, hipStream_t stream);
+// Counts words of a and b whose bits differ; *d_count must be a device int.
+int launch_count_mismatch(const float* a, const float* b, size_t n, unsigned* d_count,
+                          hipStream_t stream);
+int launch_flush(float* d, size_t n, hipStream_t stream);
+
+// ---------------------------------------------------------------- JSON lines
+// Minimal flat-object JSON: string, number and number-array values.
+struct JsonObj {
+    std::map<std::string, std::string> str;
+    std::map<std::string, double> num;
+    std::map<std::string, std::vector<double>> arr;
+};
+std::string json_escape(const std::string& s);
+bool json_parse_line(const std::string& line, JsonObj* out);
+bool append_line(const std::string& path, const std::string& line);
+
+// ---------------------------------------------------------------- winners cache
+std::string winners_default_path();
+int cache_lookup(const std::string& path, const std::string& arch, const conv2d_shape& s,
+                 conv2d_config* c, double* ms);
+int cache_store(const std::string& path, const std::string& arch, const conv2d_shape& s,
+                const conv2d_config& c, double ms);
+
+}  // namespace conv2d

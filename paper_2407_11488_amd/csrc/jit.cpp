@@ -1,0 +1,131 @@
+// Run-time compilation of the tunable direct-convolution kernel with hiprtc,
+// an on-disk code-object cache, and module loading.
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+#include <mutex>
+
+#include "internal.h"
+
+namespace conv2d {
+
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wc23-extensions"
+static const char kDirectSource[] = {
+#embed "conv2d_direct.hip"
+    , 0};
+#pragma clang diagnostic pop
+
+const std::string& direct_source()
+{
+    static const std::string s(kDirectSource);
+    return s;
+}
+
+uint64_t direct_source_hash()
+{
+    static const uint64_t h = fnv1a(direct_source());
+    return h;
+}
+
+std::vector<std::string> direct_options(const conv2d_shape& s, const conv2d_config& c, int vin,
+                                        int vout, const std::string& arch)
+{
+    auto D = [](const char* k, int v) { return std::string("-D") + k + "=" + std::to_string(v); };
+    return {
+        "--offload-arch=" + arch,
+        "-O3",
+        "-std=c++17",
+        // Packed FP32 instructions are never generated (each FMA is a plain
+        // v_fmac_f32 / v_fma_f32).
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        D("CONV_BX", c.block_x), D("CONV_BY", c.block_y), D("CONV_TX", c.tile_x),
+        D("CONV_TY", c.tile_y), D("CONV_USE_LDS", c.use_lds), D("CONV_FCONST", c.filter_in_const),
+        D("CONV_UNROLL", c.unroll), D("CONV_FH", s.filt_h), D("CONV_FW", s.filt_w),
+        D("CONV_VIN", vin), D("CONV_VOUT", vout),
+    };
+}
+
+std::string code_cache_dir()
+{
+    std::string d = env_str("CONV2D_CACHE_DIR");
+    if (d.empty()) d = library_dir() + "/_cache";
+    return d;
+}
+
+static std::string hiprtc_version_str()
+{
+    int maj = 0, min = 0;
+    hiprtcVersion(&maj, &min);
+    return std::to_string(maj) + "." + std::to_string(min);
+}
+
+int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int vout,
+                   const std::string& arch, std::vector<char>* code, std::string* path)
+{
+    const std::vector<std::string> opts = direct_options(s, c, vin, vout, arch);
+    uint64_t h = direct_source_hash();
+    h = fnv1a(hiprtc_version_str(), h);
+    for (const auto& o : opts) h = fnv1a(o + "\x1f", h);
+    const std::string dir = code_cache_dir();
+    const std::string file = dir + "/direct_" + hex64(h) + ".co";
+    if (path) *path = file;
+    std::vector<char> cached;
+    if (read_file(file, cached) && cached.size() > 64) {
+        if (code) code->swap(cached);
+        return CONV2D_OK;
+    }
+
+    hiprtcProgram prog = nullptr;
+    if (hiprtcCreateProgram(&prog, kDirectSource, "conv2d_direct.hip", 0, nullptr, nullptr) !=
+        HIPRTC_SUCCESS)
+        return fail(CONV2D_ECOMPILE, "hiprtcCreateProgram failed");
+    std::vector<const char*> argv;
+    for (const auto& o : opts) argv.push_back(o.c_str());
+    hiprtcResult r = hiprtcCompileProgram(prog, (int)argv.size(), argv.data());
+    if (r != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        hiprtcGetProgramLogSize(prog, &n);
+        std::string log(n + 1, '\0');
+        if (n) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(CONV2D_ECOMPILE, "config " + config_str(c) + ": " + log.c_str());
+    }
+    size_t n = 0;
+    hiprtcGetCodeSize(prog, &n);
+    std::vector<char> obj(n);
+    hiprtcGetCode(prog, obj.data());
+    hiprtcDestroyProgram(&prog);
+    if (make_dirs(dir)) write_file_atomic(file, obj.data(), obj.size());  // best effort
+    if (code) code->swap(obj);
+    return CONV2D_OK;
+}
+
+int load_module(const std::vector<char>& code, Module* m)
+{
+    *m = Module{};
+    CONV2D_HIP(hipModuleLoadData(&m->mod, code.data()));
+    hipError_t e = hipModuleGetFunction(&m->fn, m->mod, "conv2d_direct");
+    if (e != hipSuccess) {
+        hipModuleUnload(m->mod);
+        m->mod = nullptr;
+        return hip_fail(e, "hipModuleGetFunction(conv2d_direct)");
+    }
+    hipDeviceptr_t p = nullptr;
+    size_t bytes = 0;
+    if (hipModuleGetGlobal(&p, &bytes, m->mod, "conv_filter") == hipSuccess) {
+        m->const_filter = p;
+        m->const_bytes = bytes;
+    } else {
+        (void)hipGetLastError();
+    }
+    return CONV2D_OK;
+}
+
+void unload_module(Module* m)
+{
+    if (m && m->mod) hipModuleUnload(m->mod);
+    if (m) *m = Module{};
+}
+
+}  // namespace conv2d

@@ -1,0 +1,95 @@
+// Host emulation of the HIP device features the convolution kernels use, so
+// the kernel sources compile as ordinary C++ and run on the CPU under
+// AddressSanitizer: every GPU thread of a workgroup is a host thread, and
+// __syncthreads() is a real barrier. Raw buffer loads keep their hardware
+// meaning (an offset at or past num_records reads 0) and additionally check
+// that every in-range read lies inside the allocation the buffer describes.
+// Test infrastructure only.
+#pragma once
+
+#include <barrier>
+#include <cassert>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __constant__
+#define __shared__ static
+
+struct emu_dim3 {
+    unsigned x = 0, y = 0, z = 0;
+};
+extern thread_local emu_dim3 threadIdx;
+extern thread_local emu_dim3 blockIdx;
+extern emu_dim3 blockDim;
+extern emu_dim3 gridDim;
+extern std::barrier<>* emu_block_barrier;
+
+inline void __syncthreads() { emu_block_barrier->arrive_and_wait(); }
+
+struct __amdgpu_buffer_rsrc_t {
+    const char* base;
+    uint32_t num_records;
+};
+
+inline __amdgpu_buffer_rsrc_t __builtin_amdgcn_make_buffer_rsrc(void* p, short stride, int num, int flags)
+{
+    assert(stride == 0 && flags == 0x00020000);
+    return {static_cast<const char*>(p), static_cast<uint32_t>(num)};
+}
+
+// Bytes [off, off+n) of the buffer; each dword outside num_records reads 0.
+inline void emu_buffer_read(__amdgpu_buffer_rsrc_t r, int off, int n, uint32_t* out)
+{
+    for (int k = 0; k < n; ++k) {
+        const uint64_t o = (uint64_t)(uint32_t)off + 4ull * k;
+        if (o + 4 > r.num_records) {
+            out[k] = 0;
+        } else {
+            std::memcpy(&out[k], r.base + o, 4);  // ASan checks the allocation
+        }
+    }
+}
+
+typedef unsigned int emu_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int emu_u32x4 __attribute__((ext_vector_type(4)));
+
+inline unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
+{
+    assert(soff == 0 && aux == 0);
+    uint32_t v;
+    emu_buffer_read(r, off, 1, &v);
+    return v;
+}
+
+inline emu_u32x2 __builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
+{
+    assert(soff == 0 && aux == 0 && (off & 7) == 0);
+    uint32_t v[2];
+    emu_buffer_read(r, off, 2, v);
+    return emu_u32x2{v[0], v[1]};
+}
+
+inline emu_u32x4 __builtin_amdgcn_raw_buffer_load_b128(__amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
+{
+    assert(soff == 0 && aux == 0 && (off & 15) == 0);
+    uint32_t v[4];
+    emu_buffer_read(r, off, 4, v);
+    return emu_u32x4{v[0], v[1], v[2], v[3]};
+}
+
+template <class T>
+inline void emu_nontemporal_store(T v, T* p)
+{
+    // Vector stores must be naturally aligned, as on the GPU.
+    assert(reinterpret_cast<uintptr_t>(p) % sizeof(T) == 0);
+    *p = v;
+}
+#define __builtin_nontemporal_store(v, p) emu_nontemporal_store(v, p)

@@ -1,0 +1,191 @@
+"""GPU parity of the plain path (conv2d_plan / conv2d_run) against the FP64
+oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests.gpu_util import TOL, nan_like, precompile, run_config, say, to_dev, torch_cuda, vec_class
+
+pytestmark = pytest.mark.gpu
+
+C = pytest.importorskip("paper_2407_11488_amd")
+
+
+def _check_uniform(out_dev, inp, filt, tol=TOL):
+    ref, s = oracle.conv2d_f64(inp, filt)
+    got = out_dev.cpu().numpy()
+    assert np.all(np.isfinite(got)), "unwritten (NaN) outputs"
+    err = oracle.normalized_error(got, ref, s)
+    assert err <= tol, f"normalised error {err:.3e} > {tol}"
+    return got
+
+
+def test_device_generator_matches_host():
+    torch = torch_cuda()
+    n = 1 << 20
+    d = torch.empty(n, dtype=torch.float32, device="cuda")
+    say("fill_uniform seed 7 start 123")
+    C.conv2d_fill_uniform(d.data_ptr(), n, 7, 123, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), datagen.uniform_pm1(7, n, start=123).view(np.uint32))
+
+
+def test_reference_kernel_matches_oracle():
+    for (H, W, fh, fw) in [(1, 1, 1, 1), (37, 53, 17, 17), (64, 3, 5, 9), (5, 200, 31, 3)]:
+        inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=3, seed_f=4)
+        say(f"reference {H}x{W} f{fh}x{fw}")
+        out = C.reference(to_dev(inp), to_dev(f))
+        torch_cuda().cuda.synchronize()
+        _check_uniform(out, inp, f)
+        ia, fa = datagen.conv_problem(H, W, fh, fw, kind="int")
+        out = C.reference(to_dev(ia), to_dev(fa))
+        ref, _ = oracle.conv2d_f64(ia, fa)
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+
+
+def test_plain_workload_default_config():
+    """Output 1024x1024, filter 17x17, input 1040x1040 with a zero halo, the
+    default configuration, no tuning."""
+    inp, f = datagen.conv_problem(1024, 1024, 17, 17, zero_halo=True)
+    say("plain 1024x1024 f17 default config")
+    out = run_config(C, to_dev(inp), to_dev(f), C.conv2d_default_config())
+    _check_uniform(out, inp, f)
+
+
+def test_whole_space_integer_data_bitwise():
+    """Every one of the 1216 configurations on a ragged shape that spans several
+    tiles: integer data makes every partial sum exact, so each configuration
+    must equal the oracle bit for bit."""
+    H, W, fh, fw = 70, 45, 5, 3
+    s = C.shape(H, W, fh, fw)
+    every = C.conv2d_space(s, 1, -1)
+    assert len(every) == 1216
+    cfgs = [c for c in every if C.conv2d_config_check(s, c) == 0]
+    illegal = [c for c in every if c not in cfgs]
+    assert all(C.conv2d_lds_bytes(fh, fw, c) > 163840 for c in illegal)
+    for c in illegal:
+        with pytest.raises(C.Conv2dError):
+            C.conv2d_plan(s, c)
+    precompile(C, s, cfgs, vec_class(W + fw - 1), vec_class(W))
+    inp, f = datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=8, seed_f=9)
+    ref, _ = oracle.conv2d_f64(inp, f)
+    di, df = to_dev(inp), to_dev(f)
+    bad = []
+    for k, c in enumerate(cfgs):
+        if k % 200 == 0:
+            say(f"whole space: config {k}/{len(cfgs)} {c}")
+        got = run_config(C, di, df, c).cpu().numpy().astype(np.float64)
+        if not np.array_equal(got, ref):
+            bad.append(c)
+    assert not bad, f"{len(bad)} configurations differ, first {bad[:5]}"
+
+
+STRATIFIED = [
+    (16, 16, 1, 1, 1, 1), (16, 1, 1, 1, 0, 0), (32, 2, 2, 4, 0, 1), (64, 1, 2, 4, 0, 0), (64, 1, 8, 8, 0, 0),
+    (64, 1, 8, 8, 1, 0), (64, 4, 4, 8, 1, 1), (128, 1, 8, 4, 0, 1), (128, 8, 1, 2, 1, 0), (16, 16, 8, 8, 0, 0),
+    (32, 16, 4, 1, 1, 1), (128, 4, 2, 8, 0, 0), (64, 2, 1, 8, 1, 0), (16, 4, 8, 2, 1, 1), (128, 1, 4, 1, 1, 1),
+    (32, 8, 8, 1, 0, 1),
+]
+
+
+@pytest.mark.parametrize("fh,fw", [(17, 17), (3, 3), (7, 7), (15, 15), (31, 31), (1, 1), (5, 9), (9, 5),
+                                   (1, 7), (7, 1)])
+def test_stratified_configs_uniform(fh, fw):
+    """Uniform data on a ragged shape: each configuration within tolerance of the
+    oracle, no unwritten outputs, and all configurations bitwise identical
+    (fixed accumulation order)."""
+    H, W = 203, 317
+    s = C.shape(H, W, fh, fw)
+    cfgs = [c + (1,) for c in STRATIFIED if C.conv2d_config_check(s, c + (1,)) == 0]
+    precompile(C, s, cfgs, vec_class(W + fw - 1), vec_class(W))
+    inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=10 + fh, seed_f=20 + fw)
+    di, df = to_dev(inp), to_dev(f)
+    first = None
+    for c in cfgs:
+        say(f"uniform {H}x{W} f{fh}x{fw} cfg {c}")
+        got = _check_uniform(run_config(C, di, df, c), inp, f)
+        if first is None:
+            first = got
+        else:
+            assert np.array_equal(got.view(np.uint32), first.view(np.uint32)), c
+
+
+@pytest.mark.parametrize("cfg", [(64, 1, 8, 8, 0, 0, 1), (16, 16, 1, 1, 1, 1, 1), (64, 2, 4, 4, 1, 0, 2),
+                                 (64, 1, 2, 4, 0, 1, 0), (32, 4, 8, 2, 0, 0, 4)])
+def test_unroll_and_alignment_variants(cfg):
+    """Unroll factors, and misaligned input/output pointers (views offset by one
+    float), which take the unaligned-vector module."""
+    torch = torch_cuda()
+    H, W, fh, fw = 129, 260, 17, 17
+    inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=31, seed_f=32)
+    say(f"unroll/alignment cfg {cfg}")
+    out = run_config(C, to_dev(inp), to_dev(f), cfg)
+    _check_uniform(out, inp, f)
+    big_in = torch.zeros(inp.size + 1, dtype=torch.float32, device="cuda")
+    big_in[1:] = to_dev(inp).reshape(-1)
+    big_out = torch.full((H * W + 1,), float("nan"), dtype=torch.float32, device="cuda")
+    s = C.shape(H, W, fh, fw)
+    plan = C.conv2d_plan(s, cfg)
+    try:
+        C.conv2d_run(plan, big_in.data_ptr() + 4, to_dev(f).data_ptr(), big_out.data_ptr() + 4,
+                     torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+    finally:
+        C.conv2d_destroy(plan)
+    got = big_out[1:].reshape(H, W)
+    assert np.array_equal(got.cpu().numpy().view(np.uint32), out.cpu().numpy().view(np.uint32))
+
+
+def test_full_size_sampled():
+    """4096x4096 / 17x17 (the tuned workload) with the configuration the plan
+    picks: sampled outputs (corners, edges, random interior) against the oracle
+    computed point by point; every output finite."""
+    torch = torch_cuda()
+    H = W = 4096
+    fh = fw = 17
+    n_in = (H + fh - 1) * (W + fw - 1)
+    inp = datagen.uniform_pm1(1, n_in).reshape(H + fh - 1, W + fw - 1)
+    f = datagen.uniform_pm1(2, fh * fw).reshape(fh, fw)
+    plan = C.Plan(H, W, fh, fw)
+    say(f"full size 4096 f17 with {plan.source} config {plan.config}")
+    out = plan(to_dev(inp), to_dev(f), out=nan_like(H, W))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    rng = np.random.default_rng(5)
+    ys = np.concatenate([[0, 0, H - 1, H - 1], rng.integers(0, H, 3000), np.full(50, H - 1), np.arange(50)])
+    xs = np.concatenate([[0, W - 1, 0, W - 1], rng.integers(0, W, 3000), rng.integers(0, W, 50),
+                         np.full(50, W - 1)])
+    ref, s = oracle.conv2d_points_f64(inp, f, ys, xs)
+    err = oracle.normalized_error(got[ys, xs], ref, s)
+    assert err <= TOL, err
+    plan.close()
+
+
+def test_errors_are_reported_not_faulted():
+    torch = torch_cuda()
+    s = C.shape(64, 64, 5, 5)
+    plan = C.conv2d_plan(s, (64, 1, 4, 4, 0, 0, 1))
+    try:
+        inp = torch.zeros((68, 68), dtype=torch.float32, device="cuda")
+        f = torch.zeros((5, 5), dtype=torch.float32, device="cuda")
+        out = torch.empty((64, 64), dtype=torch.float32, device="cuda")
+        st = torch.cuda.current_stream().cuda_stream
+        with pytest.raises(C.Conv2dError) as e:
+            C.conv2d_run(plan, inp.data_ptr(), f.data_ptr(), 0, st)
+        assert e.value.status == C.CONV2D_EINVAL
+        with pytest.raises(C.Conv2dError):
+            C.conv2d_run(plan, inp.data_ptr() + 2, f.data_ptr(), out.data_ptr(), st)  # misaligned
+        host = np.zeros(64 * 64, np.float32)
+        with pytest.raises(C.Conv2dError):
+            C.conv2d_run(plan, inp.data_ptr(), f.data_ptr(), host.ctypes.data, st)
+        with pytest.raises(C.Conv2dError):
+            C.conv2d_run(plan, inp.data_ptr(), f.data_ptr(), inp.data_ptr(), st)  # aliasing
+        torch.cuda.synchronize()
+    finally:
+        C.conv2d_destroy(plan)
+    with pytest.raises(C.Conv2dError):
+        C.conv2d_plan(C.shape(0, 5, 3, 3), None)
+    with pytest.raises(C.Conv2dError):
+        C.conv2d_plan(C.shape(8, 8, 64, 3), None)

@@ -1,0 +1,108 @@
+"""The tunable kernel source run on the CPU (tests/emu): one host thread per GPU
+thread, real barriers, bounds-checked buffer loads, AddressSanitizer and
+UBSan. Each configuration must equal the FP64 oracle bit for bit on integer
+data (exact in any order), write every output, and make no out-of-bounds
+access, on pitches of every alignment class. No GPU needed."""
+import concurrent.futures as cf
+import hashlib
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EMU = os.path.join(HERE, "emu")
+KERNEL = os.path.join(os.path.dirname(HERE), "paper_2407_11488_amd", "csrc", "conv2d_direct.hip")
+CXX = "/opt/rocm/llvm/bin/clang++"
+BIN_DIR = os.path.join(tempfile.gettempdir(), "conv2d_emu_bins")
+
+# (block_x, block_y) x tiles x lds x const, plus unroll variants; kept small
+# enough for the CPU suite. CONV2D_EMU_FULL=1 runs the whole 1216-point space.
+BLOCKS = [(16, 1), (64, 1), (32, 4), (16, 16), (128, 2)]
+TILES = [(1, 1), (2, 4), (4, 1), (8, 8), (4, 2), (1, 8)]
+
+
+def sample_configs():
+    if os.environ.get("CONV2D_EMU_FULL") == "1":
+        return [(bx, by, tx, ty, l, c, 1) for bx in (16, 32, 64, 128) for by in (1, 2, 4, 8, 16)
+                for tx in (1, 2, 4, 8) for ty in (1, 2, 4, 8) for l in (0, 1) for c in (0, 1) if bx * by <= 1024]
+    out = []
+    for k, (bx, by) in enumerate(BLOCKS):
+        for j, (tx, ty) in enumerate(TILES):
+            for lds in (0, 1):
+                out.append((bx, by, tx, ty, lds, (k + j + lds) % 2, 1))
+    out += [(64, 1, 8, 8, 0, 0, 0), (64, 2, 4, 4, 1, 1, 2), (32, 1, 2, 8, 0, 1, 4), (16, 4, 8, 2, 1, 0, 0)]
+    return out
+
+
+# (H, W, fh, fw): odd pitch (vector width 1), pitch = 2 mod 4, pitch = 0 mod 4,
+# and a shape smaller than one tile.
+SHAPES = [(21, 45, 5, 3), (13, 36, 3, 3), (9, 72, 7, 5), (3, 5, 2, 4)]
+
+
+def vec_class(n):
+    return 4 if n % 4 == 0 else (2 if n % 2 == 0 else 1)
+
+
+def build(cfg, fh, fw, vin, vout):
+    bx, by, tx, ty, lds, fc, un = cfg
+    defs = dict(BX=bx, BY=by, TX=tx, TY=ty, USE_LDS=lds, FCONST=fc, UNROLL=un, FH=fh, FW=fw, VIN=vin, VOUT=vout)
+    src = open(KERNEL).read() + open(os.path.join(EMU, "emu_direct.cpp")).read() + \
+        open(os.path.join(EMU, "hip_emu.h")).read()
+    key = hashlib.sha1((src + repr(sorted(defs.items()))).encode()).hexdigest()[:16]
+    os.makedirs(BIN_DIR, exist_ok=True)
+    exe = os.path.join(BIN_DIR, f"emu_{key}")
+    if not os.path.exists(exe):
+        cmd = [CXX, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+               "-fno-omit-frame-pointer", *[f"-DCONV_{k}={v}" for k, v in defs.items()],
+               os.path.join(EMU, "emu_direct.cpp"), "-o", exe + ".tmp", "-lpthread"]
+        subprocess.run(cmd, check=True, capture_output=True)
+        os.replace(exe + ".tmp", exe)
+    return exe
+
+
+def run(exe, inp, f, H, W, tmp):
+    pi, pf, po = (os.path.join(tmp, n) for n in ("in.f32", "f.f32", "out.f32"))
+    inp.astype(np.float32).tofile(pi)
+    f.astype(np.float32).tofile(pf)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+    r = subprocess.run([exe, pi, pf, po, str(H), str(W)], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return np.fromfile(po, np.float32).reshape(H, W)
+
+
+@pytest.fixture(scope="module")
+def binaries():
+    jobs = []
+    for (H, W, fh, fw) in SHAPES:
+        for cfg in sample_configs():
+            lds_rows = cfg[1] * cfg[3] + fh - 1
+            lds_cols = cfg[0] * cfg[2] + fw - 1
+            if cfg[4] and lds_rows * (lds_cols + 8) * 4 > 163840:
+                continue
+            jobs.append(((H, W, fh, fw), cfg))
+    with cf.ThreadPoolExecutor(os.cpu_count() or 4) as ex:
+        futs = {job: ex.submit(build, job[1], job[0][2], job[0][3], vec_class(job[0][1] + job[0][3] - 1),
+                               vec_class(job[0][1])) for job in jobs}
+        return {job: f.result() for job, f in futs.items()}
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_emulated_kernel_exact(binaries, shape, tmp_path):
+    H, W, fh, fw = shape
+    inp, f = datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=H, seed_f=W)
+    ref, _ = oracle.conv2d_f64(inp, f)
+    n = 0
+    for (shp, cfg), exe in binaries.items():
+        if shp != shape:
+            continue
+        got = run(exe, inp, f, H, W, str(tmp_path))
+        assert np.all(np.isfinite(got)), f"unwritten outputs for {cfg}"
+        assert np.array_equal(got.astype(np.float64), ref), f"config {cfg} differs from the oracle"
+        n += 1
+    assert n > 20
