@@ -169,6 +169,7 @@ typedef struct conv2d_tune_opts {
     int unroll;                /* unroll value for every point (default 1) */
     int max_configs;           /* 0: whole space, else the first N legal points (tests) */
     double tie_rel;            /* relative tie window for the winner (default 0.005) */
+    int verbose;               /* 1: progress lines on stderr */
 } conv2d_tune_opts;
 
 typedef struct conv2d_tune_result {

@@ -78,7 +78,7 @@ class Config(ctypes.Structure):
 class TuneOpts(ctypes.Structure):
     _fields_ = [("winners_path", c_char_p), ("results_path", c_char_p), ("warmup", c_int), ("reps", c_int),
                 ("retime_reps", c_int), ("flush_mall", c_int), ("threads", c_int), ("unroll", c_int),
-                ("max_configs", c_int), ("tie_rel", c_double)]
+                ("max_configs", c_int), ("tie_rel", c_double), ("verbose", c_int)]
 
 
 class TuneResult(ctypes.Structure):

@@ -258,6 +258,8 @@ public:
             });
         for (auto& th : pool) th.join();
         *seconds = now_s() - t0;
+        if (o_.verbose)
+            std::fprintf(stderr, "[tune] compiled %zu configurations in %.1f s\n", cfgs.size(), *seconds);
         return CONV2D_OK;
     }
 
@@ -434,6 +436,8 @@ int tune_core(const conv2d_shape& s, const conv2d_tune_opts& o, Measurer* meas, 
         }
         done[config_str(r.c)] = r;
         if (o.results_path && *o.results_path) append_line(o.results_path, result_line(meas->arch(), s, r));
+        if (o.verbose && ((i + 1) % 100 == 0 || i + 1 == todo.size()))
+            std::fprintf(stderr, "[tune] measured %zu/%zu, best %.4f ms\n", i + 1, todo.size(), best);
     }
 
     // Collect the timed points among the candidates.
