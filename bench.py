@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--default-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed region, run plain copy/negate kernels over this many MiB "
+                         "(calibration of the profiler's byte counters)")
     return ap.parse_args()
 
 
@@ -141,6 +144,14 @@ def main():
     }
     plan.close()
     dplan.close()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)       # reads n*4 bytes, writes n*4 bytes
+        torch.cuda.synchronize()
+        line["calibration"] = {"kernel": "torch.neg elementwise", "read_bytes": n * 4, "write_bytes": n * 4}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -83,6 +83,10 @@ int conv2d_version(void);
 /* Thread-local text of the last non-zero return on this thread ("" if none). */
 const char *conv2d_last_error(void);
 
+/* Hex hash of the tunable kernel source built into this library (keys the
+ * winners cache and the code-object cache). Static storage, never NULL. */
+const char *conv2d_kernel_hash(void);
+
 /* The untuned default configuration: the textbook 16x16-thread tiled kernel,
  * one output per thread, LDS halo, filter in constant memory, unroll 1. */
 void conv2d_default_config(conv2d_config *cfg);
@@ -170,6 +174,7 @@ typedef struct conv2d_tune_opts {
     int max_configs;           /* 0: whole space, else the first N legal points (tests) */
     double tie_rel;            /* relative tie window for the winner (default 0.005) */
     int verbose;               /* 1: progress lines on stderr */
+    int refine_unroll;         /* 1: also time the ten fastest points with the other unroll values */
 } conv2d_tune_opts;
 
 typedef struct conv2d_tune_result {

@@ -14,7 +14,7 @@ from ._binding import (CONV2D_EBUSY, CONV2D_ECOMPILE, CONV2D_EHIP, CONV2D_EINVAL
                        CONV2D_ENOMEM, CONV2D_ENOTUNED, CONV2D_EVERIFY, CONV2D_OK, LIB_PATH, Config,
                        Conv2dError, Shape, TuneOpts, TuneResult, config, conv2d_cache_lookup,
                        conv2d_cache_store, conv2d_compile, conv2d_config_check, conv2d_default_config,
-                       conv2d_destroy, conv2d_fill_uniform, conv2d_geometry, conv2d_last_error,
+                       conv2d_destroy, conv2d_fill_uniform, conv2d_geometry, conv2d_kernel_hash, conv2d_last_error,
                        conv2d_lds_bytes, conv2d_plan, conv2d_plan_config, conv2d_reference, conv2d_run,
                        conv2d_space, conv2d_tune, conv2d_tune_defaults, conv2d_tune_synthetic,
                        conv2d_version, lib, shape)

@@ -12,7 +12,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libconv2d.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_11488_amd.build` "
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2407_11488_amd/build.py` "
                       "(there is no CPU fallback)")
 
 # PyTorch ships its own HIP runtime. Loading it first makes the library's
@@ -78,7 +78,8 @@ class Config(ctypes.Structure):
 class TuneOpts(ctypes.Structure):
     _fields_ = [("winners_path", c_char_p), ("results_path", c_char_p), ("warmup", c_int), ("reps", c_int),
                 ("retime_reps", c_int), ("flush_mall", c_int), ("threads", c_int), ("unroll", c_int),
-                ("max_configs", c_int), ("tie_rel", c_double), ("verbose", c_int)]
+                ("max_configs", c_int), ("tie_rel", c_double), ("verbose", c_int),
+                ("refine_unroll", c_int)]
 
 
 class TuneResult(ctypes.Structure):
@@ -96,6 +97,7 @@ P = ctypes.POINTER
 _SIGS = {
     "conv2d_version": (c_int, []),
     "conv2d_last_error": (c_char_p, []),
+    "conv2d_kernel_hash": (c_char_p, []),
     "conv2d_default_config": (None, [P(Config)]),
     "conv2d_lds_bytes": (c_int, [c_int, c_int, P(Config)]),
     "conv2d_config_check": (c_int, [Shape, P(Config), c_int]),
@@ -152,6 +154,10 @@ def conv2d_version() -> int:
 
 def conv2d_last_error() -> str:
     return lib.conv2d_last_error().decode(errors="replace")
+
+
+def conv2d_kernel_hash() -> str:
+    return lib.conv2d_kernel_hash().decode()
 
 
 def conv2d_default_config() -> Config:

@@ -1,0 +1,136 @@
+"""Search-space statistics over the tuner's results database (JSON lines, one
+per timed configuration), following the paper's Section 4 metrics:
+
+* tuning impact: best over median throughput (Table 3's statistic);
+* the distribution of throughput relative to the optimum (the violin plots of
+  Figs. 3, 5, 7, 9, summarised here as percentiles);
+* application efficiency e_i(x) = P_i(x) / max_x P_i(x) (Eq. 3), with the
+  "devices" i replaced by problem shapes on one GPU;
+* performance portability PP(x, H) = |H| / sum_i 1/e_i(x) (Eq. 2), and the
+  configuration that maximises it over a set of shapes.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+
+def results_name(arch: str, shape) -> str:
+    H, W, fh, fw = shape
+    return f"results_{arch}_{H}x{W}_{fh}x{fw}.jsonl"
+
+
+def flops(shape) -> float:
+    H, W, fh, fw = shape
+    return 2.0 * H * W * fh * fw
+
+
+def algorithmic_bytes(shape) -> int:
+    """Bytes a convolution must move at least once: input, output, filter."""
+    H, W, fh, fw = shape
+    return 4 * ((H + fh - 1) * (W + fw - 1) + H * W + fh * fw)
+
+
+def load(db: str, shape, src: str | None = None) -> dict:
+    """config tuple -> record for `shape` (the last line of a config wins)."""
+    out = {}
+    if not os.path.exists(db):
+        return out
+    with open(db) as fh:
+        for line in fh:
+            try:
+                r = json.loads(line)
+            except json.JSONDecodeError:
+                continue
+            if tuple(r.get("shape", ())) != tuple(shape) or (src and r.get("src") != src):
+                continue
+            out[tuple(int(v) for v in r["config"])] = r
+    return out
+
+
+def throughputs(db: str, shape, src: str | None = None) -> dict:
+    """config -> GFLOP/s for the configurations that compiled, ran and verified."""
+    return {c: flops(shape) / (r["ms"] * 1e-3) / 1e9 for c, r in load(db, shape, src).items()
+            if r.get("status") == "ok" and r.get("ms", 0) > 0}
+
+
+def _median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+def impact(db: str, shape, src: str | None = None) -> float:
+    p = list(throughputs(db, shape, src).values())
+    return max(p) / _median(p)
+
+
+def percentiles(db: str, shape, qs=(0, 10, 25, 50, 75, 90, 100), src: str | None = None) -> dict:
+    """Throughput relative to the optimum at the given percentiles (nearest rank)."""
+    p = sorted(throughputs(db, shape, src).values())
+    best = p[-1]
+    out = {}
+    for q in qs:
+        k = max(1, math.ceil(q / 100 * len(p))) - 1 if q > 0 else 0
+        out[f"p{q}"] = round(p[k] / best, 4)
+    return out
+
+
+def winner_of(db: str, shape, winners_path: str | None = None):
+    """The cached winner of `shape` (last entry), else the fastest in the DB."""
+    if winners_path and os.path.exists(winners_path):
+        win = None
+        with open(winners_path) as fh:
+            for line in fh:
+                try:
+                    r = json.loads(line)
+                except json.JSONDecodeError:
+                    continue
+                if tuple(r.get("shape", ())) == tuple(shape):
+                    win = tuple(int(v) for v in r["config"])
+        if win is not None:
+            return win
+    p = throughputs(db, shape)
+    return max(p, key=p.get) if p else None
+
+
+def efficiency_of(db: str, shape, cfg) -> dict:
+    """Eq. 3 for one configuration on one shape."""
+    p = throughputs(db, shape)
+    if not p:
+        return {}
+    best = max(p.values())
+    got = p.get(tuple(cfg))
+    return {"ref_config_gflops": None if got is None else round(got, 1), "own_best_gflops": round(best, 1),
+            "efficiency": None if got is None else round(got / best, 4)}
+
+
+def performance_portability(effs) -> float:
+    """Eq. 2: harmonic mean of the efficiencies (0 if any is 0 or missing)."""
+    effs = list(effs)
+    if not effs or any(e is None or e <= 0 for e in effs):
+        return 0.0
+    return len(effs) / sum(1.0 / e for e in effs)
+
+
+def portability_table(dbs: dict) -> dict:
+    """dbs: shape -> db path. Returns, for every configuration timed on every
+    shape, its efficiencies per shape and its PP over the set."""
+    per = {s: throughputs(db, s) for s, db in dbs.items()}
+    common = set.intersection(*(set(p) for p in per.values())) if per else set()
+    best = {s: max(p.values()) for s, p in per.items()}
+    table = {}
+    for c in common:
+        e = {s: per[s][c] / best[s] for s in per}
+        table[c] = {"efficiency": e, "pp": performance_portability(e.values())}
+    return table
+
+
+def most_portable(dbs: dict):
+    """The configuration with the highest PP over the shapes (ties: smallest tuple)."""
+    t = portability_table(dbs)
+    if not t:
+        return None, {}
+    c = max(sorted(t), key=lambda k: t[k]["pp"])
+    return c, t[c]

@@ -2,9 +2,10 @@
 
 Host sources (*.cpp) are compiled with amdclang++ as plain C++ against the HIP
 headers; device sources (*.hip) with hipcc for gfx950. Packed FP32
-instructions are disabled in every device compilation. Run:
+instructions are disabled in every device compilation. Run it as a script
+(importing the package would load the library before it is built):
 
-    python -m paper_2407_11488_amd.build
+    python paper_2407_11488_amd/build.py
 """
 from __future__ import annotations
 

@@ -23,6 +23,8 @@
 //   CONV_FH, CONV_FW   filter size
 //   CONV_VIN           input vector width 1/2/4 (row pitch and base aligned)
 //   CONV_VOUT          output vector width 1/2/4 (row pitch and base aligned)
+//   CONV_NAME          kernel symbol (one per configuration, so that profiles
+//                      tell configurations apart); default conv2d_direct
 //
 // Design (MI355X):
 //  * Each thread owns a TY x TX register tile of outputs, contiguous in x.
@@ -40,6 +42,10 @@
 
 #ifndef CONV_BX
 #error "CONV_BX must be defined"
+#endif
+
+#ifndef CONV_NAME
+#define CONV_NAME conv2d_direct
 #endif
 
 #define NT (CONV_BX * CONV_BY)
@@ -157,7 +163,7 @@ static __device__ __forceinline__ int xcd_remap(int id, int n_tiles)
 #endif
 
 extern "C" __global__ void __launch_bounds__(NT)
-conv2d_direct(const float* __restrict__ in, const float* __restrict__ filt,
+CONV_NAME(const float* __restrict__ in, const float* __restrict__ filt,
               float* __restrict__ out, int H, int W, int tiles_x, int n_tiles, u32 in_bytes)
 {
     const int t = xcd_remap((int)blockIdx.x, n_tiles);

@@ -62,6 +62,8 @@ std::vector<std::string> direct_options(const conv2d_shape& s, const conv2d_conf
 int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int vout,
                    const std::string& arch, std::vector<char>* code, std::string* path);
 std::string code_cache_dir();
+// Kernel symbol of one configuration, e.g. conv2d_direct_b16x16_t4x2_l1c0u1_f17x17.
+std::string direct_kernel_name(const conv2d_shape& s, const conv2d_config& c);
 
 // A loaded module with the direct kernel and its constant-filter symbol.
 struct Module {
@@ -70,7 +72,7 @@ struct Module {
     void* const_filter = nullptr;   // device address of conv_filter (FCONST=1)
     size_t const_bytes = 0;
 };
-int load_module(const std::vector<char>& code, Module* m);
+int load_module(const std::vector<char>& code, const std::string& kernel, Module* m);
 void unload_module(Module* m);
 
 // ---------------------------------------------------------------- device

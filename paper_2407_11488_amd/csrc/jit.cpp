@@ -28,6 +28,14 @@ uint64_t direct_source_hash()
     return h;
 }
 
+std::string direct_kernel_name(const conv2d_shape& s, const conv2d_config& c)
+{
+    char b[128];
+    std::snprintf(b, sizeof b, "conv2d_direct_b%dx%d_t%dx%d_l%dc%du%d_f%dx%d", c.block_x, c.block_y, c.tile_x,
+                  c.tile_y, c.use_lds, c.filter_in_const, c.unroll, s.filt_h, s.filt_w);
+    return b;
+}
+
 std::vector<std::string> direct_options(const conv2d_shape& s, const conv2d_config& c, int vin,
                                         int vout, const std::string& arch)
 {
@@ -43,6 +51,7 @@ std::vector<std::string> direct_options(const conv2d_shape& s, const conv2d_conf
         D("CONV_TY", c.tile_y), D("CONV_USE_LDS", c.use_lds), D("CONV_FCONST", c.filter_in_const),
         D("CONV_UNROLL", c.unroll), D("CONV_FH", s.filt_h), D("CONV_FW", s.filt_w),
         D("CONV_VIN", vin), D("CONV_VOUT", vout),
+        "-DCONV_NAME=" + direct_kernel_name(s, c),
     };
 }
 
@@ -101,15 +110,15 @@ int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int v
     return CONV2D_OK;
 }
 
-int load_module(const std::vector<char>& code, Module* m)
+int load_module(const std::vector<char>& code, const std::string& kernel, Module* m)
 {
     *m = Module{};
     CONV2D_HIP(hipModuleLoadData(&m->mod, code.data()));
-    hipError_t e = hipModuleGetFunction(&m->fn, m->mod, "conv2d_direct");
+    hipError_t e = hipModuleGetFunction(&m->fn, m->mod, kernel.c_str());
     if (e != hipSuccess) {
         hipModuleUnload(m->mod);
         m->mod = nullptr;
-        return hip_fail(e, "hipModuleGetFunction(conv2d_direct)");
+        return hip_fail(e, ("hipModuleGetFunction(" + kernel + ")").c_str());
     }
     hipDeviceptr_t p = nullptr;
     size_t bytes = 0;

@@ -218,7 +218,7 @@ static int build_module(conv2d_plan_s* p, int vin, int vout, Module* m)
     std::vector<char> code;
     int rc = compile_direct(p->shape, p->cfg, vin, vout, p->arch, &code, nullptr);
     if (rc) return rc;
-    return load_module(code, m);
+    return load_module(code, direct_kernel_name(p->shape, p->cfg), m);
 }
 
 extern "C" int conv2d_plan(conv2d_plan_t* plan, conv2d_shape s, const conv2d_config* cfg)
@@ -317,7 +317,8 @@ extern "C" int conv2d_run(conv2d_plan_t plan, const float* d_in, const float* d_
         m = &plan->unaligned;
     }
     if (plan->cfg.filter_in_const) {
-        if (!m->const_filter) return fail(CONV2D_EHIP, "module has no conv_filter symbol");
+        if (!m->const_filter || m->const_bytes < sizeof(float) * plan->shape.filt_h * plan->shape.filt_w)
+            return fail(CONV2D_EHIP, "module has no conv_filter symbol of the filter's size");
         CONV2D_HIP(hipMemcpyAsync(m->const_filter, d_filter,
                                   sizeof(float) * plan->shape.filt_h * plan->shape.filt_w,
                                   hipMemcpyDeviceToDevice, st));
@@ -355,4 +356,10 @@ extern "C" int conv2d_fill_uniform(float* d_out, size_t n, uint64_t seed, uint64
 extern "C" const char* conv2d_last_error(void)
 {
     return conv2d::last_error_cstr();
+}
+
+extern "C" const char* conv2d_kernel_hash(void)
+{
+    static const std::string h = hex64(direct_source_hash());
+    return h.c_str();
 }

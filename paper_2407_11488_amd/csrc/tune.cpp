@@ -245,7 +245,7 @@ public:
         for (size_t i = 0; i < cfgs.size(); ++i) index_[config_str(cfgs[i])] = i;
         int nthreads = o_.threads > 0 ? o_.threads : (int)std::thread::hardware_concurrency();
         nthreads = std::max(1, std::min(nthreads, 16));
-        std::atomic<size_t> next{0};
+        std::atomic<size_t> next{0}, compiled{0};
         std::vector<std::thread> pool;
         for (int t = 0; t < nthreads; ++t)
             pool.emplace_back([&] {
@@ -254,6 +254,9 @@ public:
                     if (i >= cfgs.size()) break;
                     if (compile_direct(s_, cfgs[i], vin_, vout_, dev_.arch, &code_[i], nullptr) != CONV2D_OK)
                         (*status)[i] = kCompile;
+                    const size_t done_n = ++compiled;
+                    if (o_.verbose && done_n % 200 == 0)
+                        std::fprintf(stderr, "[tune] compiled %zu/%zu\n", done_n, cfgs.size());
                 }
             });
         for (auto& th : pool) th.join();
@@ -270,7 +273,7 @@ public:
         if (it == index_.end()) return fail(CONV2D_EINVAL, "config not prepared");
         std::vector<char>& code = code_[it->second];
         Module m;
-        if (load_module(code, &m) != CONV2D_OK) { r->status = kLaunch; return CONV2D_OK; }
+        if (load_module(code, direct_kernel_name(s_, c), &m) != CONV2D_OK) { r->status = kLaunch; return CONV2D_OK; }
         std::vector<char>().swap(code);
         int rc = run_checked(m, c, r);
         if (rc == CONV2D_OK && r->status == kOk) rc = time_it(m, c, warmup, reps, best_so_far, r);
@@ -438,6 +441,53 @@ int tune_core(const conv2d_shape& s, const conv2d_tune_opts& o, Measurer* meas, 
         if (o.results_path && *o.results_path) append_line(o.results_path, result_line(meas->arch(), s, r));
         if (o.verbose && ((i + 1) % 100 == 0 || i + 1 == todo.size()))
             std::fprintf(stderr, "[tune] measured %zu/%zu, best %.4f ms\n", i + 1, todo.size(), best);
+    }
+
+    // Optional refinement: the ten fastest points again with every other
+    // unroll value (the partial-unroll factor the paper makes tunable).
+    if (o.refine_unroll) {
+        std::vector<Record> ok;
+        for (const auto& c : legal) {
+            const Record& r = done[config_str(c)];
+            if (r.status == kOk) ok.push_back(r);
+        }
+        std::sort(ok.begin(), ok.end(), [](const Record& a, const Record& b) { return a.ms < b.ms; });
+        if (ok.size() > 10) ok.resize(10);
+        std::vector<conv2d_config> extra;
+        for (const auto& r : ok)
+            for (int u : {0, 1, 2, 4}) {
+                conv2d_config c2 = r.c;
+                c2.unroll = u;
+                if (u == r.c.unroll || conv2d_config_check(s, &c2, meas->lds_limit()) != CONV2D_OK) continue;
+                bool seen = false;
+                for (const auto& e : extra) seen = seen || config_equal(e, c2);
+                if (!seen) extra.push_back(c2);
+            }
+        clear_error();
+        std::vector<conv2d_config> todo2;
+        for (const auto& c : extra)
+            if (!done.count(config_str(c))) todo2.push_back(c);
+        std::vector<int> st2;
+        double sec2 = 0;
+        rc = meas->prepare(todo2, &st2, &sec2);
+        if (rc) return rc;
+        res->compile_s += sec2;
+        for (size_t i = 0; i < todo2.size(); ++i) {
+            Record r;
+            r.c = todo2[i];
+            if (st2[i] != kOk) r.status = st2[i];
+            else {
+                rc = meas->measure(todo2[i], o.warmup, o.reps, best, &r);
+                if (rc) return rc;
+            }
+            done[config_str(r.c)] = r;
+            if (o.results_path && *o.results_path) append_line(o.results_path, result_line(meas->arch(), s, r));
+        }
+        for (const auto& c : extra) {
+            legal.push_back(c);
+            candidates.push_back(c);
+        }
+        if (o.verbose) std::fprintf(stderr, "[tune] refined %zu unroll variants\n", extra.size());
     }
 
     // Collect the timed points among the candidates.

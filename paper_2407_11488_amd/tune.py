@@ -1,14 +1,19 @@
 """Command-line driver of the tuner (conv2d_tune in the C library).
 
+One shape:
     python -m paper_2407_11488_amd.tune --shape 4096 4096 17 17 [--results PATH]
         [--winners PATH] [--reps 20] [--retime-reps 50] [--no-flush] [--unroll 1]
-        [--max-configs N] [--json OUT]
+        [--no-refine-unroll] [--max-configs N] [--json OUT]
 
-Prints one JSON report: the winner and its throughput, the top five, the
-median configuration, the tuning impact (best over median throughput, the
-paper's Section 4 metric), tuned/default, and compile/launch/verify failure
-counts. The winner is appended to the winners cache, which later plans of the
-same shape pick up.
+Filter-size sweep (each shape tuned, then compared with a reference shape's
+winner applied unchanged):
+    python -m paper_2407_11488_amd.tune --size 4096 --filters 3 7 15 31 --ref-filter 17 \
+        --results-dir DIR
+
+Prints JSON reports: the winner and its throughput, the top five, the median,
+the tuning impact (best over median throughput, the paper's Section 4
+metric), tuned/default, and compile/launch/verify failure counts. Winners are
+appended to the winners cache, which later plans of the same shape pick up.
 """
 from __future__ import annotations
 
@@ -18,6 +23,7 @@ import os
 import sys
 
 from . import _binding as B
+from . import analysis
 
 DEFAULT_WINNERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "winners.jsonl")
 PEAK_FP32_TFLOPS = 157.3
@@ -33,6 +39,7 @@ def report(shape, r) -> dict:
         "winner": list(r.best.tuple()),
         "best_ms": round(r.best_ms, 5),
         "best_gflops": round(r.best_gflops, 1),
+        "best_gbs": round(analysis.algorithmic_bytes(shape) / (r.best_ms * 1e-3) / 1e9, 1),
         "pct_fp32_peak": round(r.best_gflops / 1e3 / PEAK_FP32_TFLOPS * 100, 2),
         "median_gflops": round(r.median_gflops, 1),
         "impact": round(r.impact, 3),
@@ -48,9 +55,33 @@ def report(shape, r) -> dict:
     }
 
 
+def tune_one(shape, a, results_path):
+    o = B.conv2d_tune_defaults()
+    o.winners_path = a.winners.encode() if a.winners else None
+    o.results_path = results_path.encode() if results_path else None
+    o.reps, o.retime_reps, o.warmup = a.reps, a.retime_reps, a.warmup
+    o.flush_mall = 0 if a.no_flush else 1
+    o.unroll, o.max_configs, o.threads, o.verbose = a.unroll, a.max_configs, a.threads, 1
+    o.refine_unroll = 0 if a.no_refine_unroll else 1
+    r = B.conv2d_tune(B.shape(*shape), o)
+    return report(shape, r)
+
+
+def emit(rep, path):
+    line = json.dumps(rep)
+    print(line, flush=True)
+    if path:
+        with open(path, "a") as fh:
+            fh.write(line + "\n")
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--shape", type=int, nargs=4, metavar=("OUT_H", "OUT_W", "FH", "FW"), required=True)
+    ap.add_argument("--shape", type=int, nargs=4, metavar=("OUT_H", "OUT_W", "FH", "FW"))
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--filters", type=int, nargs="*")
+    ap.add_argument("--ref-filter", type=int, default=17)
+    ap.add_argument("--results-dir", default=None)
     ap.add_argument("--winners", default=DEFAULT_WINNERS)
     ap.add_argument("--results", default=None)
     ap.add_argument("--reps", type=int, default=20)
@@ -58,23 +89,32 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-flush", action="store_true")
     ap.add_argument("--unroll", type=int, default=1)
+    ap.add_argument("--no-refine-unroll", action="store_true")
     ap.add_argument("--max-configs", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
-    o = B.conv2d_tune_defaults()
-    o.winners_path = a.winners.encode() if a.winners else None
-    o.results_path = a.results.encode() if a.results else None
-    o.reps, o.retime_reps, o.warmup = a.reps, a.retime_reps, a.warmup
-    o.flush_mall = 0 if a.no_flush else 1
-    o.unroll, o.max_configs, o.threads, o.verbose = a.unroll, a.max_configs, a.threads, 1
-    r = B.conv2d_tune(B.shape(*a.shape), o)
-    rep = report(a.shape, r)
-    line = json.dumps(rep)
-    print(line, flush=True)
-    if a.json:
-        with open(a.json, "a") as fh:
-            fh.write(line + "\n")
+
+    if a.shape:
+        emit(tune_one(tuple(a.shape), a, a.results), a.json)
+        return 0
+    if not a.filters:
+        ap.error("give --shape, or --filters for a filter-size sweep")
+    rdir = a.results_dir or os.path.dirname(DEFAULT_WINNERS)
+    os.makedirs(rdir, exist_ok=True)
+    n = a.size
+    ref_shape = (n, n, a.ref_filter, a.ref_filter)
+    ref_db = os.path.join(rdir, analysis.results_name("gfx950", ref_shape))
+    for f in a.filters:
+        shape = (n, n, f, f)
+        db = os.path.join(rdir, analysis.results_name("gfx950", shape))
+        rep = tune_one(shape, a, db)
+        ref_cfg = analysis.winner_of(ref_db, ref_shape, winners_path=a.winners)
+        if ref_cfg is not None:
+            rep["ref_shape"] = list(ref_shape)
+            rep["ref_winner"] = list(ref_cfg)
+            rep.update(analysis.efficiency_of(db, shape, ref_cfg))
+        emit(rep, a.json)
     return 0
 
 

@@ -56,7 +56,7 @@ int main(int argc, char** argv)
             th_.emplace_back([=] {
                 threadIdx = {(unsigned)t, 0, 0};
                 blockIdx = {(unsigned)b, 0, 0};
-                conv2d_direct(d_in, d_f, d_out, H, W, tiles_x, n_tiles, in_bytes);
+                CONV_NAME(d_in, d_f, d_out, H, W, tiles_x, n_tiles, in_bytes);
             });
         for (auto& x : th_) x.join();
     }

@@ -1,0 +1,211 @@
+"""Host-side behaviour of the C library (no GPU): exported symbols, the search
+space and its restrictions, code-object properties of compiled
+configurations, the tile mapping, and the tuner's selection and statistics
+against the plain-Python oracle (with a synthetic cost in place of the GPU)."""
+import json
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2407_11488_amd as C
+from oracle import space as ospace
+from oracle import tuning as otune
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "conv2d.h")
+OBJDUMP = "/opt/rocm/llvm/bin/llvm-objdump"
+READELF = "/opt/rocm/llvm/bin/llvm-readelf"
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(conv2d_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(n for n in names if not n.endswith("_fn")))
+
+
+def test_library_exports_every_declared_function():
+    names = header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(C.lib, n)]
+    assert not missing, missing
+
+
+def test_space_matches_oracle_enumeration():
+    s = C.shape(4096, 4096, 17, 17)
+    got = C.conv2d_space(s, 1, -1)
+    assert got == [c + (1,) for c in ospace.restricted()]
+    legal = C.conv2d_space(s, 1, 0)
+    assert len(legal) == 1202                       # 14 points need more than 160 KiB of LDS
+    assert all(C.conv2d_lds_bytes(17, 17, c) <= 163840 for c in legal)
+    assert len(C.conv2d_space(C.shape(4096, 4096, 31, 31), 1, 0)) == 1192
+
+
+def test_config_check_errors():
+    s = C.shape(64, 64, 3, 3)
+    assert C.conv2d_config_check(s, (64, 1, 8, 8, 0, 0, 1)) == 0
+    for bad in [(48, 1, 1, 1, 0, 0, 1), (64, 3, 1, 1, 0, 0, 1), (128, 16, 1, 1, 0, 0, 1), (64, 1, 3, 1, 0, 0, 1),
+                (64, 1, 1, 1, 2, 0, 1), (64, 1, 1, 1, 0, 0, 3)]:
+        assert C.conv2d_config_check(s, bad) == C.CONV2D_EINVAL, bad
+        assert C.conv2d_last_error()
+    assert C.conv2d_config_check(C.shape(0, 4, 3, 3), (64, 1, 1, 1, 0, 0, 1)) == C.CONV2D_EINVAL
+    assert C.conv2d_config_check(C.shape(4, 4, 64, 3), (64, 1, 1, 1, 0, 0, 1)) == C.CONV2D_EINVAL
+
+
+def _notes(path):
+    out = subprocess.run([READELF, "--notes", path], capture_output=True, text=True).stdout
+    get = lambda k: int(re.search(rf"\.{k}:\s+(\d+)", out).group(1))  # noqa: E731
+    return {k: get(k) for k in ("group_segment_fixed_size", "private_segment_fixed_size", "vgpr_count",
+                                "vgpr_spill_count")}
+
+
+@pytest.mark.parametrize("cfg,vin", [((16, 16, 1, 1, 1, 1, 1), 4), ((64, 1, 8, 8, 1, 0, 1), 1),
+                                     ((32, 4, 4, 2, 1, 1, 1), 2), ((128, 2, 2, 8, 1, 0, 1), 4)])
+def test_lds_bytes_bound_the_compiled_kernel(cfg, vin):
+    s = C.shape(512, 512, 17, 17)
+    notes = _notes(C.conv2d_compile(s, cfg, vin, 4))
+    assert 0 < notes["group_segment_fixed_size"] <= C.conv2d_lds_bytes(17, 17, cfg)
+
+
+@pytest.mark.parametrize("cfg", [(16, 16, 4, 2, 1, 0, 1), (64, 1, 8, 8, 0, 0, 1), (128, 8, 8, 2, 0, 1, 1),
+                                 (64, 1, 2, 4, 0, 1, 1)])
+def test_compiled_code_is_plain_fp32_fma_without_spills(cfg):
+    """No packed FP32 instruction anywhere; the row loop's body holds exactly
+    tile_y*tile_x*17 single FMAs (rolled loop, unroll 1); no scratch."""
+    s = C.shape(4096, 4096, 17, 17)
+    path = C.conv2d_compile(s, cfg, 4, 4)
+    isa = subprocess.run([OBJDUMP, "-d", path], capture_output=True, text=True).stdout
+    assert "v_pk_" not in isa
+    assert isa.count("v_fmac_f32") + isa.count("v_fma_f32") == cfg[2] * cfg[3] * 17
+    n = _notes(path)
+    assert n["private_segment_fixed_size"] == 0 and n["vgpr_spill_count"] == 0
+
+
+def xcd_remap(i, n):
+    q, rem = n >> 3, n & 7
+    x, k = i & 7, i >> 3
+    return x * q + min(x, rem) + k
+
+
+def test_xcd_remap_is_a_bijection():
+    for n in list(range(1, 70)) + [4095, 4096, 8191, 65536 + 3]:
+        t = [xcd_remap(i, n) for i in range(n)]
+        assert sorted(t) == list(range(n)), n
+
+
+@pytest.mark.parametrize("shape", [(70, 45, 5, 3), (1, 1, 1, 1), (4096, 4096, 17, 17), (203, 317, 31, 31)])
+def test_tiles_cover_every_output_once(shape):
+    """Model of the kernel's index mapping (workgroup -> tile via the XCD
+    remap, thread -> tile_y x tile_x outputs): every output of the image is
+    owned by exactly one thread, for a sample of configurations."""
+    H, W, fh, fw = shape
+    s = C.shape(*shape)
+    rng = np.random.default_rng(1)
+    cfgs = C.conv2d_space(s, 1, 0)
+    for idx in rng.choice(len(cfgs), size=12, replace=False):
+        c = cfgs[idx]
+        bx, by, tx, ty = c[:4]
+        tiles_x, tiles_y, nt = C.conv2d_geometry(s, c)
+        assert nt == bx * by and tiles_x == -(-W // (bx * tx)) and tiles_y == -(-H // (by * ty))
+        if H * W > 1 << 20:
+            continue
+        count = np.zeros((H + by * ty, W + bx * tx), np.int32)
+        n_tiles = tiles_x * tiles_y
+        for wg in range(n_tiles):
+            t = xcd_remap(wg, n_tiles)
+            ty_, tx_ = divmod(t, tiles_x)
+            y0 = ty_ * by * ty
+            x0 = tx_ * bx * tx
+            count[y0:y0 + by * ty, x0:x0 + bx * tx] += 1
+        assert np.all(count[:H, :W] == 1), c
+
+
+# ---------------------------------------------------------------- tuner with a synthetic cost
+
+def _cost_table(seed=3):
+    rng = np.random.default_rng(seed)
+    cfgs = C.conv2d_space(C.shape(4096, 4096, 17, 17), 1, 0)
+    return {c: float(rng.uniform(0.1, 5.0)) for c in cfgs}
+
+
+def test_synthetic_tuner_matches_statistics_oracle(tmp_path):
+    table = _cost_table()
+    # two near-ties with the fastest: the smaller tuple within 0.5 % must win
+    fastest = min(table, key=table.get)
+    others = sorted(c for c in table if c < fastest)
+    if others:
+        table[others[0]] = table[fastest] * 1.004
+    winners = tmp_path / "w.jsonl"
+    results = tmp_path / "r.jsonl"
+    o = C.conv2d_tune_defaults()
+    o.winners_path, o.results_path = str(winners).encode(), str(results).encode()
+    s = C.shape(4096, 4096, 17, 17)
+    r = C.conv2d_tune_synthetic(s, lambda c: table[c], o)
+    assert r.best.tuple() == otune.pick_winner(table)
+    assert [r.top[k].tuple() for k in range(5)] == otune.top_k(table, 5)
+    perf = [2 * 4096 * 4096 * 289 / (t * 1e-3) / 1e9 for t in table.values()]
+    assert r.impact == pytest.approx(otune.tuning_impact(perf), rel=1e-12)
+    assert r.median_gflops == pytest.approx(otune.median(perf), rel=1e-12)
+    assert r.n_space == 1216 and r.n_illegal == 14 and r.n_timed == 1202
+    d = (16, 16, 1, 1, 1, 1, 1)
+    assert r.default_ms == table[d]
+    assert r.default_rank == 1 + sum(1 for t in table.values() if t < table[d])
+    # the winners cache and the results DB
+    assert C.conv2d_cache_lookup(str(winners), "synthetic", s)[0].tuple() == r.best.tuple()
+    lines = [json.loads(x) for x in open(results)]
+    assert len(lines) == 1202 and all(x["status"] == "ok" for x in lines)
+    # resume: nothing is measured again, the same winner comes out
+    calls = []
+    r2 = C.conv2d_tune_synthetic(s, lambda c: calls.append(c) or table[c], o)
+    assert r2.n_resumed == 1202 and r2.best.tuple() == r.best.tuple()
+    assert len(calls) <= 10          # only the re-timing of the top five
+
+
+def test_synthetic_tuner_records_failures(tmp_path):
+    table = _cost_table(5)
+    fail = {}
+    for k, c in enumerate(sorted(table)):
+        if k % 97 == 0:
+            fail[c] = C.CONV2D_ECOMPILE
+        elif k % 89 == 0:
+            fail[c] = C.CONV2D_ELAUNCH
+        elif k % 83 == 0:
+            fail[c] = C.CONV2D_EVERIFY
+    cost = lambda c: float(fail.get(c, table[c]))  # noqa: E731
+    r = C.conv2d_tune_synthetic(C.shape(4096, 4096, 17, 17), cost, None)
+    assert r.n_compile_fail == sum(1 for v in fail.values() if v == C.CONV2D_ECOMPILE)
+    assert r.n_launch_fail == sum(1 for v in fail.values() if v == C.CONV2D_ELAUNCH)
+    assert r.n_verify_fail == sum(1 for v in fail.values() if v == C.CONV2D_EVERIFY)
+    ok = {c: t for c, t in table.items() if c not in fail}
+    assert r.best.tuple() == otune.pick_winner(ok)
+
+
+def test_refine_unroll_adds_variants():
+    table = _cost_table(7)
+    s = C.shape(4096, 4096, 17, 17)
+    o = C.conv2d_tune_defaults()
+    o.refine_unroll = 1
+    best_plain = min(table, key=table.get)
+    # unroll 2 of the fastest point is faster still
+    cost = lambda c: table[c[:6] + (1,)] * (0.9 if c[6] == 2 and c[:6] == best_plain[:6] else 1.0)  # noqa: E731
+    r = C.conv2d_tune_synthetic(s, cost, o)
+    assert r.best.tuple() == best_plain[:6] + (2,)
+
+
+def test_cache_prefers_current_kernel_source(tmp_path):
+    p = tmp_path / "w.jsonl"
+    s = C.shape(100, 200, 5, 5)
+    old = {"arch": "gfx950", "src": "0000000000000000", "shape": [100, 200, 5, 5], "config": [64, 1, 8, 8, 0, 0, 1],
+           "ms": 1.0}
+    p.write_text(json.dumps(old) + "\n{not json\n")
+    c, ms = C.conv2d_cache_lookup(str(p), "gfx950", s)
+    assert c.tuple() == (64, 1, 8, 8, 0, 0, 1)                     # stale entry used as a fallback
+    C.conv2d_cache_store(str(p), "gfx950", s, (32, 2, 4, 4, 1, 1, 2), 0.5)
+    p.write_text(p.read_text() + json.dumps(old) + "\n")           # a later stale line does not win
+    c, ms = C.conv2d_cache_lookup(str(p), "gfx950", s)
+    assert c.tuple() == (32, 2, 4, 4, 1, 1, 2) and ms == 0.5
+    assert C.conv2d_cache_lookup(str(p), "gfx942", s) is None
+    assert C.conv2d_cache_lookup(str(p), "gfx950", C.shape(100, 200, 3, 3)) is None
