@@ -138,7 +138,8 @@ int conv2d_cache_store(const char *path, const char *arch, conv2d_shape s,
 int conv2d_plan(conv2d_plan_t *plan, conv2d_shape s, const conv2d_config *cfg);
 
 /* The configuration a plan uses, and whether it came from the winners cache
- * (*tuned = 1), was forced or given (2), or is the default (0). */
+ * (*tuned = 1; 3 when that entry was tuned with an older revision of the
+ * kernel source), was forced or given (2), or is the default (0). */
 int conv2d_plan_config(conv2d_plan_t plan, conv2d_config *cfg, int *tuned);
 
 /* Enqueues one convolution on `stream`. With filter_in_const = 1 the filter is
@@ -159,6 +160,101 @@ int conv2d_reference(conv2d_shape s, const float *d_in, const float *d_filter, f
  * splitmix64 recipe (hash element start+k of `seed`, mapped to
  * (top24 - 2^23) * 2^-23), on `stream`. */
 int conv2d_fill_uniform(float *d_out, size_t n, uint64_t seed, uint64_t start, void *stream);
+
+/* ---------------------------------------------------------------- batched path
+ *
+ * Many convolutions of uneven sizes in one hipGraph launch (not part of the
+ * paper: the batching extension of its convolution kernel). Problems are
+ * grouped by filter size; each group runs the tuned configuration of its filter
+ * size (winners cache entry for 4096x4096 with that filter, else the most
+ * recent entry with that filter, else the default; the filter is always read
+ * through its pointer) as one persistent kernel over the group's tiles. The
+ * groups are parallel branches of one graph captured at plan time. Results
+ * are bitwise identical to conv2d_run / conv2d_reference on the same data.
+ * A batch plan must not run on two streams at once (its descriptor table is
+ * shared); runs on one stream are ordered. Each input is limited to 2 GiB. */
+
+enum {
+    CONV2D_BATCH_NO_GRAPH = 1,     /* launch the group kernels directly instead of a graph */
+    CONV2D_BATCH_NO_PTR_CHECK = 2  /* skip the per-problem allocation checks */
+};
+
+/* Plans n problems (n <= 65535); shapes[i] as for conv2d_plan. */
+int conv2d_batch_plan(conv2d_batch_t *batch, int n, const conv2d_shape *shapes, int flags);
+
+/* Enqueues all n convolutions on `stream`: d_in[i], d_f[i], d_out[i] are the
+ * device buffers of problem i (host arrays of n device pointers). When the
+ * pointers differ from the previous run, a 48-byte-per-problem descriptor
+ * table is first copied to the device on the same stream. */
+int conv2d_batch_run(conv2d_batch_t batch, const float *const *d_in, const float *const *d_f,
+                     float *const *d_out, void *stream);
+
+/* Groups of a batch: their count, the total tile count, and for the first
+ * `cap` groups the filter size (filt[2g], filt[2g+1]), configuration and
+ * persistent grid size. Any output pointer may be NULL. */
+int conv2d_batch_info(conv2d_batch_t batch, int *n_groups, int *total_tiles, int *filt,
+                      conv2d_config *cfgs, int *grids, int cap);
+
+void conv2d_batch_destroy(conv2d_batch_t batch);
+
+/* Compiles the batched kernel of a configuration (filter read through its
+ * pointer, scalar loads and stores) for gfx950 with hiprtc, no GPU needed.
+ * Only s.filt_h and s.filt_w matter. */
+int conv2d_compile_batch(conv2d_shape s, const conv2d_config *cfg, char *path_out, int path_cap);
+
+/* ---------------------------------------------------------------- serving
+ *
+ * A trace of requests run with continuous batching (not part of the paper:
+ * the serving extension of its convolution kernel). Requests queue FIFO in
+ * arrival order and are admitted while their device memory (input, filter
+ * and, unless kept, output) fits `hbm_budget`; an admitted request's image
+ * and filter are generated on the device from its seeds (the recipe of
+ * conv2d_fill_uniform), standing in for an image that arrives in HBM. When
+ * one of `streams` streams is free, every admitted request not yet launched
+ * (up to max_batch) is launched as one batch: one fill launch, then one
+ * persistent batched kernel per filter size present (as in conv2d_batch_run).
+ * Batches on different streams overlap on the device. A request's latency
+ * runs from its arrival time to the host observing its batch's completion
+ * event; outputs stay on the device. serial_plain = 1 runs the same trace one
+ * request at a time through the plain kernel (the baseline). Results are
+ * bitwise identical to a plain conv2d_run of the same data. */
+
+typedef struct conv2d_request {
+    double arrival_s;       /* seconds from the start of the run, non-decreasing */
+    conv2d_shape shape;
+    uint64_t seed_in;       /* image seed */
+    uint64_t seed_f;        /* filter seed */
+} conv2d_request;
+
+typedef struct conv2d_serve_opts {
+    size_t hbm_budget;      /* device bytes for admitted requests (default 8 GiB) */
+    int streams;            /* batches in flight at once, 1..16 (default 4) */
+    int max_batch;          /* requests per batch, 1..32767 (default 64) */
+    int serial_plain;       /* 1: one at a time through the plain kernel */
+    int keep_outputs;       /* 1: each output in its own allocation, returned in outputs[] */
+} conv2d_serve_opts;
+
+typedef struct conv2d_serve_report {
+    int n_requests, n_batches;
+    double wall_s;          /* first arrival to last completion */
+    double req_per_s, gflops, offered_rate;
+    double p50_ms, p99_ms, mean_ms, max_ms;      /* latency, nearest-rank percentiles */
+    double queue_p50_ms, queue_p99_ms;           /* arrival to launch */
+    double mean_batch;
+    int stalled_requests;   /* requests that waited for HBM budget */
+    size_t peak_bytes;      /* peak admitted bytes */
+    double late_start_ms;   /* serial run: worst launch delay behind schedule */
+} conv2d_serve_report;
+
+void conv2d_serve_defaults(conv2d_serve_opts *opts);
+
+/* Runs reqs[0..n) (blocking). latency_ms (may be NULL) receives each
+ * request's latency; with keep_outputs, outputs[i] receives a device pointer
+ * to request i's output (release with conv2d_serve_free). */
+int conv2d_serve(const conv2d_request *reqs, int n, const conv2d_serve_opts *opts,
+                 conv2d_serve_report *report, double *latency_ms, float **outputs);
+
+void conv2d_serve_free(float **outputs, int n);
 
 /* ---------------------------------------------------------------- tuner */
 
@@ -205,6 +301,13 @@ void conv2d_tune_defaults(conv2d_tune_opts *opts);
  * smallest configuration tuple) and stored in the winners cache. Inputs are
  * the seeded uniform recipe (input seed 1, filter seed 2), on device. */
 int conv2d_tune(conv2d_shape s, const conv2d_tune_opts *opts, conv2d_tune_result *res);
+
+/* Times one configuration the way the tuner does: seeded inputs on the
+ * device, one verified launch (bitwise against the reference kernel), then
+ * `warmup` untimed and `reps` timed launches (HIP events, optional cache flush
+ * before each). Writes the median and minimum milliseconds. */
+int conv2d_benchmark(conv2d_shape s, const conv2d_config *cfg, int warmup, int reps, int flush_mall,
+                     double *median_ms, double *min_ms);
 
 /* The same search with a caller-supplied cost instead of the GPU (a fake
  * backend for host tests): cost(cfg, user) returns a time in ms, or a

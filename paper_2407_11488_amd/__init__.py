@@ -13,9 +13,13 @@ from __future__ import annotations
 from ._binding import (CONV2D_EBUSY, CONV2D_ECOMPILE, CONV2D_EHIP, CONV2D_EINVAL, CONV2D_ELAUNCH,  # noqa: F401
                        CONV2D_ENOMEM, CONV2D_ENOTUNED, CONV2D_EVERIFY, CONV2D_OK, LIB_PATH, Config,
                        Conv2dError, Shape, TuneOpts, TuneResult, config, conv2d_cache_lookup,
-                       conv2d_cache_store, conv2d_compile, conv2d_config_check, conv2d_default_config,
+                       conv2d_benchmark, conv2d_cache_store, conv2d_compile, conv2d_config_check, conv2d_default_config,
                        conv2d_destroy, conv2d_fill_uniform, conv2d_geometry, conv2d_kernel_hash, conv2d_last_error,
                        conv2d_lds_bytes, conv2d_plan, conv2d_plan_config, conv2d_reference, conv2d_run,
                        conv2d_space, conv2d_tune, conv2d_tune_defaults, conv2d_tune_synthetic,
                        conv2d_version, lib, shape)
-from .api import Plan, conv2d, reference  # noqa: F401
+from ._binding import (CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK, conv2d_batch_destroy,  # noqa: F401
+                       conv2d_batch_info, conv2d_batch_plan, conv2d_batch_run, conv2d_compile_batch)
+from ._binding import (REQUEST_DTYPE, ServeOpts, ServeReport, conv2d_serve, conv2d_serve_defaults,  # noqa: F401
+                       conv2d_serve_free, requests_array)
+from .api import Batch, Plan, conv2d, reference  # noqa: F401

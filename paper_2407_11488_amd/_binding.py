@@ -115,6 +115,7 @@ _SIGS = {
     "conv2d_tune_defaults": (None, [P(TuneOpts)]),
     "conv2d_tune": (c_int, [Shape, P(TuneOpts), P(TuneResult)]),
     "conv2d_tune_synthetic": (c_int, [Shape, COST_FN, c_void_p, P(TuneOpts), P(TuneResult)]),
+    "conv2d_benchmark": (c_int, [Shape, P(Config), c_int, c_int, c_int, P(c_double), P(c_double)]),
 }
 
 
@@ -261,3 +262,129 @@ def conv2d_tune_synthetic(s: Shape, cost, opts: TuneOpts | None = None) -> TuneR
     check(lib.conv2d_tune_synthetic(s, cb, None, None if opts is None else ctypes.byref(opts),
                                     ctypes.byref(r)), "conv2d_tune_synthetic")
     return r
+
+
+def conv2d_benchmark(s: Shape, cfg, warmup: int = 2, reps: int = 20, flush_mall: int = 1):
+    """(median_ms, min_ms) of one verified configuration."""
+    med, mn = c_double(), c_double()
+    check(lib.conv2d_benchmark(s, ctypes.byref(config(cfg)), warmup, reps, flush_mall, ctypes.byref(med),
+                               ctypes.byref(mn)), "conv2d_benchmark")
+    return med.value, mn.value
+
+
+CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK = 1, 2
+
+for _name, (_res, _args) in {
+    "conv2d_batch_plan": (c_int, [P(c_void_p), c_int, P(Shape), c_int]),
+    "conv2d_batch_run": (c_int, [c_void_p, P(c_void_p), P(c_void_p), P(c_void_p), c_void_p]),
+    "conv2d_batch_info": (c_int, [c_void_p, P(c_int), P(c_int), P(c_int), P(Config), P(c_int), c_int]),
+    "conv2d_batch_destroy": (None, [c_void_p]),
+    "conv2d_compile_batch": (c_int, [Shape, P(Config), c_char_p, c_int]),
+}.items():
+    _fn = getattr(lib, _name)
+    _fn.restype, _fn.argtypes = _res, _args
+
+
+def conv2d_batch_plan(shapes, flags: int = 0) -> int:
+    arr = (Shape * len(shapes))(*[s if isinstance(s, Shape) else Shape(*s) for s in shapes])
+    h = c_void_p()
+    check(lib.conv2d_batch_plan(ctypes.byref(h), len(shapes), arr, flags), "conv2d_batch_plan")
+    return h.value
+
+
+def conv2d_batch_run(batch: int, d_in, d_f, d_out, stream: int = 0) -> None:
+    n = len(d_in)
+    a = (c_void_p * n)(*d_in)
+    b = (c_void_p * n)(*d_f)
+    c = (c_void_p * n)(*d_out)
+    check(lib.conv2d_batch_run(batch, a, b, c, stream), "conv2d_batch_run")
+
+
+def conv2d_batch_info(batch: int, cap: int = 64) -> dict:
+    ng, tiles = c_int(), c_int()
+    filt = (c_int * (2 * cap))()
+    cfgs = (Config * cap)()
+    grids = (c_int * cap)()
+    check(lib.conv2d_batch_info(batch, ctypes.byref(ng), ctypes.byref(tiles), filt, cfgs, grids, cap),
+          "conv2d_batch_info")
+    groups = [{"filter": (filt[2 * g], filt[2 * g + 1]), "config": cfgs[g].tuple(), "grid": grids[g]}
+              for g in range(min(ng.value, cap))]
+    return {"n_groups": ng.value, "total_tiles": tiles.value, "groups": groups}
+
+
+def conv2d_batch_destroy(batch: int) -> None:
+    lib.conv2d_batch_destroy(batch)
+
+
+def conv2d_compile_batch(s: Shape, cfg) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    check(lib.conv2d_compile_batch(s, ctypes.byref(config(cfg)), buf, 4096), "conv2d_compile_batch")
+    return buf.value.decode()
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", c_size_t), ("streams", c_int), ("max_batch", c_int), ("serial_plain", c_int),
+                ("keep_outputs", c_int)]
+
+
+class ServeReport(ctypes.Structure):
+    _fields_ = [("n_requests", c_int), ("n_batches", c_int), ("wall_s", c_double), ("req_per_s", c_double),
+                ("gflops", c_double), ("offered_rate", c_double), ("p50_ms", c_double), ("p99_ms", c_double),
+                ("mean_ms", c_double), ("max_ms", c_double), ("queue_p50_ms", c_double),
+                ("queue_p99_ms", c_double), ("mean_batch", c_double), ("stalled_requests", c_int),
+                ("peak_bytes", c_size_t), ("late_start_ms", c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# numpy mirror of conv2d_request (40 bytes: double, 4 x int32, 2 x uint64)
+REQUEST_DTYPE = [("arrival_s", "<f8"), ("out_h", "<i4"), ("out_w", "<i4"), ("filt_h", "<i4"), ("filt_w", "<i4"),
+                 ("seed_in", "<u8"), ("seed_f", "<u8")]
+
+for _name, (_res, _args) in {
+    "conv2d_serve_defaults": (None, [P(ServeOpts)]),
+    "conv2d_serve": (c_int, [c_void_p, c_int, P(ServeOpts), P(ServeReport), P(c_double), P(c_void_p)]),
+    "conv2d_serve_free": (None, [P(c_void_p), c_int]),
+}.items():
+    _fn = getattr(lib, _name)
+    _fn.restype, _fn.argtypes = _res, _args
+
+
+def conv2d_serve_defaults() -> ServeOpts:
+    o = ServeOpts()
+    lib.conv2d_serve_defaults(ctypes.byref(o))
+    return o
+
+
+def requests_array(arrivals, shapes, seeds_in, seeds_f):
+    import numpy as np
+    a = np.zeros(len(arrivals), dtype=REQUEST_DTYPE)
+    a["arrival_s"] = arrivals
+    sh = np.asarray(shapes, dtype=np.int64).reshape(-1, 4)
+    a["out_h"], a["out_w"], a["filt_h"], a["filt_w"] = sh[:, 0], sh[:, 1], sh[:, 2], sh[:, 3]
+    a["seed_in"] = np.asarray(seeds_in, dtype=np.uint64)
+    a["seed_f"] = np.asarray(seeds_f, dtype=np.uint64)
+    assert a.dtype.itemsize == 40
+    return a
+
+
+def conv2d_serve(reqs, opts: ServeOpts | None = None, keep_outputs: bool = False):
+    """reqs: numpy array of REQUEST_DTYPE. Returns (report, latencies_ms, outputs)
+    where outputs is a list of device pointers (keep_outputs) or None."""
+    import numpy as np
+    reqs = np.ascontiguousarray(reqs)
+    n = len(reqs)
+    o = opts or conv2d_serve_defaults()
+    o.keep_outputs = 1 if keep_outputs else 0
+    rep = ServeReport()
+    lat = np.zeros(n, np.float64)
+    outs = (c_void_p * n)() if keep_outputs else None
+    check(lib.conv2d_serve(reqs.ctypes.data, n, ctypes.byref(o), ctypes.byref(rep),
+                           lat.ctypes.data_as(P(c_double)), outs), "conv2d_serve")
+    return rep, lat, (list(outs) if keep_outputs else None)
+
+
+def conv2d_serve_free(outputs) -> None:
+    arr = (c_void_p * len(outputs))(*outputs)
+    lib.conv2d_serve_free(arr, len(outputs))

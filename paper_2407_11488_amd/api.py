@@ -34,7 +34,7 @@ class Plan:
         self.handle = B.conv2d_plan(self.shape, config)
         cfg, src = B.conv2d_plan_config(self.handle)
         self.config = cfg.tuple()
-        self.source = {0: "default", 1: "tuned", 2: "given"}.get(src, str(src))
+        self.source = {0: "default", 1: "tuned", 2: "given", 3: "tuned-older-kernel"}.get(src, str(src))
 
     def __call__(self, inp, filt, out=None, stream=None):
         torch = _torch()
@@ -84,3 +84,38 @@ def reference(inp, filt, out=None, stream=None):
         out = torch.empty((H, W), dtype=torch.float32, device=inp.device)
     B.conv2d_reference(B.shape(H, W, fh, fw), inp.data_ptr(), filt.data_ptr(), out.data_ptr(), _stream(stream))
     return out
+
+
+class Batch:
+    """Many convolutions (uneven sizes, mixed filter sizes) run by one graph launch."""
+
+    def __init__(self, shapes, flags=0):
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.handle = B.conv2d_batch_plan(self.shapes, flags)
+        self.info = B.conv2d_batch_info(self.handle)
+
+    def __call__(self, inputs, filters, outputs=None, stream=None):
+        torch = _torch()
+        if len(inputs) != len(self.shapes) or len(filters) != len(self.shapes):
+            raise ValueError("one input and one filter per problem")
+        if outputs is None:
+            outputs = [torch.empty((H, W), dtype=torch.float32, device=inputs[0].device)
+                       for (H, W, _, _) in self.shapes]
+        for k, (H, W, fh, fw) in enumerate(self.shapes):
+            _check_tensor(inputs[k], f"inputs[{k}]", (H + fh - 1, W + fw - 1))
+            _check_tensor(filters[k], f"filters[{k}]", (fh, fw))
+            _check_tensor(outputs[k], f"outputs[{k}]", (H, W))
+        B.conv2d_batch_run(self.handle, [t.data_ptr() for t in inputs], [t.data_ptr() for t in filters],
+                           [t.data_ptr() for t in outputs], _stream(stream))
+        return outputs
+
+    def close(self):
+        if self.handle:
+            B.conv2d_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

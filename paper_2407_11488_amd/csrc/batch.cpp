@@ -1,0 +1,343 @@
+// Batched path: many convolutions of uneven sizes in one hipGraph launch.
+//
+// Problems are grouped by filter size (compile-time in the kernel). Each
+// group gets the tuned configuration of its filter size and one persistent
+// kernel that walks the group's tile list; the problems are described in
+// device memory (pointers, sizes, first tile), so the graph is captured once
+// at plan time, with the groups as parallel branches, and a run is one
+// hipGraphLaunch (after a small descriptor upload when the caller's pointers
+// changed since the last run).
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <memory>
+#include <mutex>
+
+#include "internal.h"
+
+namespace conv2d {
+namespace {
+
+struct Group {
+    int fh = 0, fw = 0;
+    conv2d_config cfg{};
+    Module mod;
+    std::vector<int> problems;   // indices into the batch's shapes
+    int total_tiles = 0;
+    int grid = 0;
+    int threads = 0;
+    size_t desc_begin = 0;       // first descriptor of the group
+    size_t owner_begin = 0;      // first owner entry of the group
+    // kernel arguments, kept alive for graph capture and direct launches
+    const void* a_desc = nullptr;
+    const void* a_owner = nullptr;
+    int a_total = 0;
+};
+
+}  // namespace
+}  // namespace conv2d
+
+using namespace conv2d;
+
+struct conv2d_batch_s {
+    int device = -1;
+    DeviceInfo dev;
+    int flags = 0;
+    std::vector<conv2d_shape> shapes;
+    std::vector<Group> groups;
+    std::vector<int> desc_slot;          // problem -> descriptor index
+    ConvDesc* h_desc = nullptr;          // pinned staging
+    ConvDesc* d_desc = nullptr;
+    unsigned short* d_owner = nullptr;
+    std::vector<const void*> uploaded;   // pointers of the descriptors on the device
+    hipEvent_t copied = nullptr;
+    bool copy_pending = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::mutex mu;
+};
+
+static void batch_free(conv2d_batch_s* b)
+{
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->copied) {
+        hipEventSynchronize(b->copied);
+        hipEventDestroy(b->copied);
+    }
+    for (auto& g : b->groups) unload_module(&g.mod);
+    if (b->h_desc) hipHostFree(b->h_desc);
+    if (b->d_desc) hipFree(b->d_desc);
+    if (b->d_owner) hipFree(b->d_owner);
+    delete b;
+}
+
+static int launch_group(const Group& g, hipStream_t st)
+{
+    return launch_batch_kernel(g.mod, g.cfg, g.grid, g.a_desc, g.a_owner, g.a_total, st);
+}
+
+// Captures every group's kernel as a parallel branch of one graph.
+static int capture(conv2d_batch_s* b)
+{
+    std::vector<hipStream_t> streams(b->groups.size() + 1, nullptr);
+    std::vector<hipEvent_t> events(b->groups.size() + 1, nullptr);
+    int rc = CONV2D_OK;
+    auto cleanup = [&] {
+        for (auto s : streams)
+            if (s) hipStreamDestroy(s);
+        for (auto e : events)
+            if (e) hipEventDestroy(e);
+    };
+    for (size_t k = 0; k < streams.size(); ++k) {
+        if (hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&events[k], hipEventDisableTiming) != hipSuccess) {
+            cleanup();
+            return fail(CONV2D_EHIP, "batch: cannot create capture streams");
+        }
+    }
+    hipStream_t root = streams[0];
+    hipError_t e = hipStreamBeginCapture(root, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipStreamBeginCapture"); }
+    hipEventRecord(events[0], root);
+    for (size_t g = 0; g < b->groups.size() && rc == CONV2D_OK; ++g) {
+        hipStream_t st = streams[g + 1];
+        hipStreamWaitEvent(st, events[0], 0);
+        rc = launch_group(b->groups[g], st);
+        hipEventRecord(events[g + 1], st);
+        hipStreamWaitEvent(root, events[g + 1], 0);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(root, &graph);
+    if (rc == CONV2D_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+    if (rc == CONV2D_OK) {
+        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
+    }
+    if (graph) {
+        if (rc == CONV2D_OK) b->graph = graph;
+        else hipGraphDestroy(graph);
+    }
+    cleanup();
+    return rc;
+}
+
+namespace conv2d {
+
+int batch_module_for_filter(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m)
+{
+    std::string wp = env_str("CONV2D_WINNERS");
+    if (wp.empty()) wp = winners_default_path();
+    const conv2d_shape tuned_shape{4096, 4096, fh, fw};
+    if (cache_lookup_filter(wp, dev.arch, fh, fw, tuned_shape, cfg) != CONV2D_OK) conv2d_default_config(cfg);
+    clear_error();
+    cfg->filter_in_const = 0;  // each problem has its own filter
+    if (conv2d_config_check(tuned_shape, cfg, dev.lds_limit) != CONV2D_OK) {
+        conv2d_default_config(cfg);
+        cfg->filter_in_const = 0;
+        clear_error();
+    }
+    std::vector<char> code;
+    int rc = compile_direct(tuned_shape, *cfg, 1, 1, dev.arch, &code, nullptr, true);
+    if (rc) return rc;
+    return load_module(code, direct_kernel_name(tuned_shape, *cfg, true), m);
+}
+
+int launch_batch_kernel(const Module& m, const conv2d_config& cfg, int grid, const void* d_desc,
+                        const void* d_owner, int total_tiles, hipStream_t st)
+{
+    const void* d = d_desc;
+    const void* o = d_owner;
+    int total = total_tiles;
+    void* args[] = {&d, &o, &total};
+    hipError_t e = hipModuleLaunchKernel(m.fn, (unsigned)grid, 1, 1, (unsigned)(cfg.block_x * cfg.block_y), 1, 1, 0,
+                                         st, args, nullptr);
+    if (e != hipSuccess) return fail(CONV2D_ELAUNCH, std::string("batch launch: ") + hipGetErrorString(e));
+    return CONV2D_OK;
+}
+
+}  // namespace conv2d
+
+extern "C" int conv2d_batch_plan(conv2d_batch_t* out, int n, const conv2d_shape* shapes, int flags)
+{
+    clear_error();
+    if (!out) return fail(CONV2D_EINVAL, "batch is NULL");
+    *out = nullptr;
+    if (n < 1 || !shapes) return fail(CONV2D_EINVAL, "a batch needs n >= 1 shapes");
+    if (n > 65535) return fail(CONV2D_EINVAL, "a batch holds at most 65535 problems");
+    for (int i = 0; i < n; ++i) {
+        int rc = shape_check(shapes[i]);
+        if (rc) return fail(rc, "problem " + std::to_string(i) + ": " + last_error_cstr());
+        const long long bytes = 4ll * (shapes[i].out_h + shapes[i].filt_h - 1) * (shapes[i].out_w + shapes[i].filt_w - 1);
+        if (bytes > INT_MAX) return fail(CONV2D_EINVAL, "problem " + std::to_string(i) + ": input above 2 GiB");
+    }
+    std::unique_ptr<conv2d_batch_s, void (*)(conv2d_batch_s*)> b(new conv2d_batch_s, batch_free);
+    int rc = current_device_info(&b->dev);
+    if (rc) return rc;
+    b->device = b->dev.device;
+    b->flags = flags;
+    b->shapes.assign(shapes, shapes + n);
+
+    // Group by filter size, heaviest filters first.
+    std::map<std::pair<int, int>, std::vector<int>> by_filter;
+    for (int i = 0; i < n; ++i) by_filter[{shapes[i].filt_h, shapes[i].filt_w}].push_back(i);
+    std::vector<std::pair<int, int>> keys;
+    for (auto& kv : by_filter) keys.push_back(kv.first);
+    std::sort(keys.begin(), keys.end(), [](auto a, auto c) { return a.first * a.second > c.first * c.second; });
+
+    std::vector<unsigned short> owner;
+    std::vector<ConvDesc> proto;
+    b->desc_slot.assign(n, -1);
+    for (const auto& key : keys) {
+        Group g;
+        g.fh = key.first;
+        g.fw = key.second;
+        g.problems = by_filter[key];
+        rc = batch_module_for_filter(b->dev, g.fh, g.fw, &g.cfg, &g.mod);
+        if (rc) return rc;
+        g.threads = g.cfg.block_x * g.cfg.block_y;
+        g.desc_begin = proto.size();
+        g.owner_begin = owner.size();
+        for (size_t k = 0; k < g.problems.size(); ++k) {
+            const conv2d_shape& s = shapes[g.problems[k]];
+            Geometry geo = geometry(s.out_h, s.out_w, g.cfg);
+            ConvDesc d{};
+            d.H = s.out_h;
+            d.W = s.out_w;
+            d.tiles_x = geo.tiles_x;
+            d.tile_begin = g.total_tiles;
+            d.in_bytes = (unsigned)(4ull * (s.out_h + s.filt_h - 1) * (s.out_w + s.filt_w - 1));
+            d.n_tiles = geo.n_tiles;
+            if ((long long)g.total_tiles + geo.n_tiles > INT_MAX)
+                return fail(CONV2D_EINVAL, "batch: too many tiles in one filter group");
+            g.total_tiles += geo.n_tiles;
+            owner.insert(owner.end(), (size_t)geo.n_tiles, (unsigned short)k);
+            b->desc_slot[g.problems[k]] = (int)proto.size();
+            proto.push_back(d);
+        }
+        int per_cu = 0;
+        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g.mod.fn, g.threads, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        g.grid = std::max(8, std::min(g.total_tiles, per_cu * b->dev.cus));
+        b->groups.push_back(std::move(g));
+    }
+
+    // Device tables: descriptors (pointers filled at run time) and tile owners.
+    if (hipHostMalloc((void**)&b->h_desc, sizeof(ConvDesc) * n, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&b->d_desc, sizeof(ConvDesc) * n) != hipSuccess ||
+        hipMalloc((void**)&b->d_owner, sizeof(unsigned short) * owner.size()) != hipSuccess)
+        return fail(CONV2D_ENOMEM, "batch: allocation of the descriptor tables failed");
+    std::memcpy(b->h_desc, proto.data(), sizeof(ConvDesc) * n);
+    CONV2D_HIP(hipMemcpy(b->d_owner, owner.data(), sizeof(unsigned short) * owner.size(), hipMemcpyHostToDevice));
+    CONV2D_HIP(hipEventCreateWithFlags(&b->copied, hipEventDisableTiming));
+    for (auto& g : b->groups) {
+        g.a_desc = b->d_desc + g.desc_begin;
+        g.a_owner = b->d_owner + g.owner_begin;
+        g.a_total = g.total_tiles;
+    }
+    if (!(flags & CONV2D_BATCH_NO_GRAPH)) {
+        rc = capture(b.get());
+        if (rc) return rc;
+    }
+    *out = b.release();
+    return CONV2D_OK;
+}
+
+extern "C" int conv2d_batch_run(conv2d_batch_t b, const float* const* d_in, const float* const* d_f,
+                                float* const* d_out, void* stream)
+{
+    clear_error();
+    if (!b || !d_in || !d_f || !d_out) return fail(CONV2D_EINVAL, "batch and pointer arrays must be non-NULL");
+    int dev = -1;
+    CONV2D_HIP(hipGetDevice(&dev));
+    if (dev != b->device) return fail(CONV2D_EINVAL, "batch was planned for another device");
+    const int n = (int)b->shapes.size();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(b->mu);
+
+    std::vector<const void*> ptrs(3 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        ptrs[3 * i] = d_in[i];
+        ptrs[3 * i + 1] = d_f[i];
+        ptrs[3 * i + 2] = d_out[i];
+    }
+    if (ptrs != b->uploaded) {
+        if (!(b->flags & CONV2D_BATCH_NO_PTR_CHECK)) {
+            for (int i = 0; i < n; ++i) {
+                const conv2d_shape& s = b->shapes[i];
+                const size_t in_b = 4ull * ((size_t)s.out_h + s.filt_h - 1) * ((size_t)s.out_w + s.filt_w - 1);
+                const size_t f_b = 4ull * s.filt_h * s.filt_w, o_b = 4ull * s.out_h * s.out_w;
+                int rc = check_device_range(d_in[i], in_b, "d_in");
+                if (!rc) rc = check_device_range(d_f[i], f_b, "d_filter");
+                if (!rc) rc = check_device_range(d_out[i], o_b, "d_out");
+                if (rc) return fail(rc, "problem " + std::to_string(i) + ": " + last_error_cstr());
+                const uintptr_t o = (uintptr_t)d_out[i], a = (uintptr_t)d_in[i], f = (uintptr_t)d_f[i];
+                if ((o < a + in_b && a < o + o_b) || (o < f + f_b && f < o + o_b))
+                    return fail(CONV2D_EINVAL, "problem " + std::to_string(i) + ": d_out overlaps its inputs");
+            }
+        }
+        // The staging buffer may still feed the previous upload.
+        if (b->copy_pending) CONV2D_HIP(hipEventSynchronize(b->copied));
+        for (int i = 0; i < n; ++i) {
+            ConvDesc& d = b->h_desc[b->desc_slot[i]];
+            d.in = d_in[i];
+            d.filt = d_f[i];
+            d.out = d_out[i];
+        }
+        CONV2D_HIP(hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(ConvDesc) * n, hipMemcpyHostToDevice, st));
+        CONV2D_HIP(hipEventRecord(b->copied, st));
+        b->copy_pending = true;
+        b->uploaded = ptrs;
+    }
+    if (b->exec) {
+        hipError_t e = hipGraphLaunch(b->exec, st);
+        if (e != hipSuccess) return fail(CONV2D_ELAUNCH, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        return CONV2D_OK;
+    }
+    for (const auto& g : b->groups) {
+        int rc = launch_group(g, st);
+        if (rc) return rc;
+    }
+    return CONV2D_OK;
+}
+
+extern "C" int conv2d_batch_info(conv2d_batch_t b, int* n_groups, int* total_tiles, int* filt, conv2d_config* cfgs,
+                                 int* grids, int cap)
+{
+    clear_error();
+    if (!b) return fail(CONV2D_EINVAL, "batch is NULL");
+    int tiles = 0;
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        tiles += b->groups[g].total_tiles;
+        if ((int)g < cap) {
+            if (filt) { filt[2 * g] = b->groups[g].fh; filt[2 * g + 1] = b->groups[g].fw; }
+            if (cfgs) cfgs[g] = b->groups[g].cfg;
+            if (grids) grids[g] = b->groups[g].grid;
+        }
+    }
+    if (n_groups) *n_groups = (int)b->groups.size();
+    if (total_tiles) *total_tiles = tiles;
+    return CONV2D_OK;
+}
+
+extern "C" void conv2d_batch_destroy(conv2d_batch_t b) { batch_free(b); }
+
+extern "C" int conv2d_compile_batch(conv2d_shape s, const conv2d_config* cfg, char* path_out, int path_cap)
+{
+    clear_error();
+    if (!cfg) return fail(CONV2D_EINVAL, "cfg is NULL");
+    conv2d_config c = *cfg;
+    c.filter_in_const = 0;
+    int rc = conv2d_config_check(s, &c, 0);
+    if (rc) return rc;
+    std::string path;
+    rc = compile_direct(s, c, 1, 1, env_str("CONV2D_ARCH", "gfx950"), nullptr, &path, true);
+    if (rc) return rc;
+    if (path_out && path_cap > 0) {
+        std::strncpy(path_out, path.c_str(), (size_t)path_cap - 1);
+        path_out[path_cap - 1] = '\0';
+    }
+    return CONV2D_OK;
+}

@@ -25,6 +25,8 @@
 //   CONV_VOUT          output vector width 1/2/4 (row pitch and base aligned)
 //   CONV_NAME          kernel symbol (one per configuration, so that profiles
 //                      tell configurations apart); default conv2d_direct
+//   CONV_BATCH         1: build the persistent batched kernel (many images of
+//                      one filter size, described in device memory) instead
 //
 // Design (MI355X):
 //  * Each thread owns a TY x TX register tile of outputs, contiguous in x.
@@ -91,6 +93,10 @@ __constant__ float conv_filter[CONV_FH * CONV_FW];
 #define TAP(i, j) conv_filter[(i) * CONV_FW + (j)]
 #else
 #define TAP(i, j) filt[(i) * CONV_FW + (j)]
+#endif
+
+#ifndef CONV_BATCH
+#define CONV_BATCH 0
 #endif
 
 static __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, u32 bytes)
@@ -160,15 +166,18 @@ static __device__ __forceinline__ int xcd_remap(int id, int n_tiles)
 #define LDS_CHUNKS ((LDS_COLS + CONV_VIN - 1) / CONV_VIN)
 #define LDS_PITCH0 (((LDS_CHUNKS * CONV_VIN + 3) / 4) * 4)
 #define LDS_PITCH ((LDS_PITCH0 % 32 == 0) ? LDS_PITCH0 + 4 : LDS_PITCH0)
+#define LDS_FLOATS (LDS_ROWS * LDS_PITCH)
+#else
+#define LDS_FLOATS 4
 #endif
 
-extern "C" __global__ void __launch_bounds__(NT)
-CONV_NAME(const float* __restrict__ in, const float* __restrict__ filt,
-              float* __restrict__ out, int H, int W, int tiles_x, int n_tiles, u32 in_bytes)
+// One output tile of (BY*TY) x (BX*TX) at tile coordinates (tile_y, tile_x)
+// of an image. Every thread of the workgroup calls it (the LDS variant
+// contains a barrier). `lds` is the workgroup's LDS tile.
+static __device__ __forceinline__ void conv_tile(const float* __restrict__ in, const float* __restrict__ filt,
+                                                 float* __restrict__ out, int H, int W, u32 in_bytes,
+                                                 int tile_x, int tile_y, float* __restrict__ lds)
 {
-    const int t = xcd_remap((int)blockIdx.x, n_tiles);
-    const int tile_y = t / tiles_x;
-    const int tile_x = t - tile_y * tiles_x;
     const int lx = (int)threadIdx.x % CONV_BX;
     const int ly = (int)threadIdx.x / CONV_BX;
     const int x0 = tile_x * (CONV_BX * CONV_TX) + lx * CONV_TX;
@@ -177,7 +186,6 @@ CONV_NAME(const float* __restrict__ in, const float* __restrict__ filt,
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(in, in_bytes);
 
 #if CONV_USE_LDS
-    __shared__ __attribute__((aligned(16))) float tile[LDS_ROWS * LDS_PITCH];
     {
         const u32 gx0 = (u32)tile_x * (CONV_BX * CONV_TX);
         const u32 gy0 = (u32)tile_y * (CONV_BY * CONV_TY);
@@ -188,11 +196,11 @@ CONV_NAME(const float* __restrict__ in, const float* __restrict__ filt,
             buffer_row<CONV_VIN, CONV_VIN>(v, rs, ((gy0 + rr) * P + gx0 + cc) * 4u);
 #pragma unroll
             for (int m = 0; m < CONV_VIN; ++m)
-                tile[rr * LDS_PITCH + cc + m] = v[m];
+                lds[rr * LDS_PITCH + cc + m] = v[m];
         }
     }
     __syncthreads();
-    const float* lbase = tile + (ly * CONV_TY) * LDS_PITCH + lx * CONV_TX;
+    const float* lbase = lds + (ly * CONV_TY) * LDS_PITCH + lx * CONV_TX;
 #endif
 
     if (x0 >= W || y0 >= H)
@@ -259,3 +267,63 @@ CONV_NAME(const float* __restrict__ in, const float* __restrict__ filt,
         }
     }
 }
+
+#if !CONV_BATCH
+// One image: one workgroup per tile, tiles_x * tiles_y = n_tiles workgroups.
+extern "C" __global__ void __launch_bounds__(NT)
+CONV_NAME(const float* __restrict__ in, const float* __restrict__ filt,
+          float* __restrict__ out, int H, int W, int tiles_x, int n_tiles, u32 in_bytes)
+{
+    __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
+    const int t = xcd_remap((int)blockIdx.x, n_tiles);
+    const int tile_y = t / tiles_x;
+    const int tile_x = t - tile_y * tiles_x;
+    conv_tile(in, filt, out, H, W, in_bytes, tile_x, tile_y, lds);
+}
+#else
+#if CONV_FCONST
+#error "the batched kernel reads each problem's own filter through its pointer"
+#endif
+// One problem of a batch, as the host library lays it out in device memory.
+struct ConvDesc {
+    const float* in;
+    const float* filt;
+    float* out;
+    int H, W;
+    int tiles_x;
+    int tile_begin;   // first tile of this problem in the group's tile list
+    u32 in_bytes;
+    int n_tiles;      // tiles of this problem
+};
+
+// Many images with the same filter size: a persistent grid (at least 8
+// workgroups) walks the group's tile list. The tiles of XCD x (= workgroup id
+// mod 8) form one contiguous range, shared out by stride among that XCD's
+// workgroups; owner[t] names the problem of tile t.
+extern "C" __global__ void __launch_bounds__(NT)
+CONV_NAME(const ConvDesc* __restrict__ descs, const unsigned short* __restrict__ owner, int total_tiles)
+{
+    __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
+    const int G = (int)gridDim.x;
+    const int xcd = (int)blockIdx.x & 7;
+    const int first = (int)blockIdx.x >> 3;
+    const int stride = (G - xcd + 7) >> 3;
+    const int q = total_tiles >> 3, rem = total_tiles & 7;
+    const int begin = xcd * q + MIN_(xcd, rem);
+    const int count = q + (xcd < rem ? 1 : 0);
+    for (int k = first; k < count; k += stride) {
+        const int t = begin + k;
+        const ConvDesc* d = descs + owner[t];
+        const int lt = t - d->tile_begin;
+        if ((unsigned)lt >= (unsigned)d->n_tiles)
+            continue;  // inconsistent tables: skip rather than store out of range (uniform)
+        const int tile_y = lt / d->tiles_x;
+        const int tile_x = lt - tile_y * d->tiles_x;
+#if CONV_USE_LDS
+        if (k != first)
+            __syncthreads();  // every thread is done with the previous tile's LDS
+#endif
+        conv_tile(d->in, d->filt, d->out, d->H, d->W, d->in_bytes, tile_x, tile_y, lds);
+    }
+}
+#endif

@@ -56,14 +56,15 @@ const std::string& direct_source();
 uint64_t direct_source_hash();
 // hiprtc options for one configuration (packed FP32 disabled).
 std::vector<std::string> direct_options(const conv2d_shape& s, const conv2d_config& c,
-                                        int vin, int vout, const std::string& arch);
+                                        int vin, int vout, const std::string& arch, bool batch = false);
 // Compile (or read from the disk cache) the code object for a configuration.
 // Returns CONV2D_OK or CONV2D_ECOMPILE. Thread safe.
 int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int vout,
-                   const std::string& arch, std::vector<char>* code, std::string* path);
+                   const std::string& arch, std::vector<char>* code, std::string* path,
+                   bool batch = false);
 std::string code_cache_dir();
 // Kernel symbol of one configuration, e.g. conv2d_direct_b16x16_t4x2_l1c0u1_f17x17.
-std::string direct_kernel_name(const conv2d_shape& s, const conv2d_config& c);
+std::string direct_kernel_name(const conv2d_shape& s, const conv2d_config& c, bool batch = false);
 
 // A loaded module with the direct kernel and its constant-filter symbol.
 struct Module {
@@ -110,6 +111,38 @@ int launch_count_mismatch(const float* a, const float* b, size_t n, unsigned* d_
                           hipStream_t stream);
 int launch_flush(float* d, size_t n, hipStream_t stream);
 
+// ---------------------------------------------------------------- batched kernels
+// Mirror of the batched kernel's ConvDesc (conv2d_direct.hip, CONV_BATCH=1).
+struct ConvDesc {
+    const float* in;
+    const float* filt;
+    float* out;
+    int H, W;
+    int tiles_x;
+    int tile_begin;
+    unsigned in_bytes;
+    int n_tiles;
+};
+static_assert(sizeof(ConvDesc) == 48, "descriptor layout must match the kernel");
+
+// The tuned configuration for a filter size (4096x4096 entry of the winners
+// cache, else any entry with that filter, else the default; filter always read
+// through its pointer) and its compiled, loaded batched module.
+int batch_module_for_filter(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m);
+// Launches a batched kernel over `total_tiles` tiles on `grid` workgroups.
+int launch_batch_kernel(const Module& m, const conv2d_config& cfg, int grid, const void* d_desc,
+                        const void* d_owner, int total_tiles, hipStream_t st);
+
+// Seeded fill of many buffers in one launch (see conv2d_fill_uniform).
+struct FillDesc {
+    float* p;
+    unsigned long long n;
+    unsigned long long seed;
+    unsigned long long reserved;
+};
+static_assert(sizeof(FillDesc) == 32, "fill descriptor layout");
+int launch_fill_uniform_batch(const FillDesc* d_desc, int n_desc, unsigned long long max_n, hipStream_t st);
+
 // ---------------------------------------------------------------- JSON lines
 // Minimal flat-object JSON: string, number and number-array values.
 struct JsonObj {
@@ -124,8 +157,12 @@ bool append_line(const std::string& path, const std::string& line);
 // ---------------------------------------------------------------- winners cache
 std::string winners_default_path();
 int cache_lookup(const std::string& path, const std::string& arch, const conv2d_shape& s,
-                 conv2d_config* c, double* ms);
+                 conv2d_config* c, double* ms, bool* stale = nullptr);
 int cache_store(const std::string& path, const std::string& arch, const conv2d_shape& s,
                 const conv2d_config& c, double ms);
+// The winner for a filter size: the entry of `prefer` if cached, else the
+// most recent entry of any shape with that filter size.
+int cache_lookup_filter(const std::string& path, const std::string& arch, int fh, int fw,
+                        const conv2d_shape& prefer, conv2d_config* c);
 
 }  // namespace conv2d

@@ -28,16 +28,16 @@ uint64_t direct_source_hash()
     return h;
 }
 
-std::string direct_kernel_name(const conv2d_shape& s, const conv2d_config& c)
+std::string direct_kernel_name(const conv2d_shape& s, const conv2d_config& c, bool batch)
 {
     char b[128];
-    std::snprintf(b, sizeof b, "conv2d_direct_b%dx%d_t%dx%d_l%dc%du%d_f%dx%d", c.block_x, c.block_y, c.tile_x,
-                  c.tile_y, c.use_lds, c.filter_in_const, c.unroll, s.filt_h, s.filt_w);
+    std::snprintf(b, sizeof b, "conv2d_%s_b%dx%d_t%dx%d_l%dc%du%d_f%dx%d", batch ? "batch" : "direct", c.block_x,
+                  c.block_y, c.tile_x, c.tile_y, c.use_lds, c.filter_in_const, c.unroll, s.filt_h, s.filt_w);
     return b;
 }
 
 std::vector<std::string> direct_options(const conv2d_shape& s, const conv2d_config& c, int vin,
-                                        int vout, const std::string& arch)
+                                        int vout, const std::string& arch, bool batch)
 {
     auto D = [](const char* k, int v) { return std::string("-D") + k + "=" + std::to_string(v); };
     return {
@@ -51,7 +51,8 @@ std::vector<std::string> direct_options(const conv2d_shape& s, const conv2d_conf
         D("CONV_TY", c.tile_y), D("CONV_USE_LDS", c.use_lds), D("CONV_FCONST", c.filter_in_const),
         D("CONV_UNROLL", c.unroll), D("CONV_FH", s.filt_h), D("CONV_FW", s.filt_w),
         D("CONV_VIN", vin), D("CONV_VOUT", vout),
-        "-DCONV_NAME=" + direct_kernel_name(s, c),
+        D("CONV_BATCH", batch ? 1 : 0),
+        "-DCONV_NAME=" + direct_kernel_name(s, c, batch),
     };
 }
 
@@ -70,9 +71,9 @@ static std::string hiprtc_version_str()
 }
 
 int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int vout,
-                   const std::string& arch, std::vector<char>* code, std::string* path)
+                   const std::string& arch, std::vector<char>* code, std::string* path, bool batch)
 {
-    const std::vector<std::string> opts = direct_options(s, c, vin, vout, arch);
+    const std::vector<std::string> opts = direct_options(s, c, vin, vout, arch, batch);
     uint64_t h = direct_source_hash();
     h = fnv1a(hiprtc_version_str(), h);
     for (const auto& o : opts) h = fnv1a(o + "\x1f", h);

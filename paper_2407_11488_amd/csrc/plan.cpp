@@ -115,7 +115,7 @@ struct conv2d_plan_s {
     std::string arch;
     conv2d_shape shape{};
     conv2d_config cfg{};
-    int source = 0;          // 0 default, 1 tuned, 2 forced/given
+    int source = 0;          // 0 default, 1 tuned, 2 forced/given, 3 tuned on an older kernel
     int vin = 1, vout = 1;   // alignment classes of the main module
     Module main;
     Module unaligned;        // vin = vout = 1, compiled on first misaligned call
@@ -248,8 +248,9 @@ extern "C" int conv2d_plan(conv2d_plan_t* plan, conv2d_shape s, const conv2d_con
         double ms = 0;
         std::string wp = env_str("CONV2D_WINNERS");
         if (wp.empty()) wp = winners_default_path();
-        if (cache_lookup(wp, dev.arch, s, &p->cfg, &ms) == CONV2D_OK) {
-            p->source = 1;
+        bool stale = false;
+        if (cache_lookup(wp, dev.arch, s, &p->cfg, &ms, &stale) == CONV2D_OK) {
+            p->source = stale ? 3 : 1;
         } else {
             conv2d_default_config(&p->cfg);
             p->source = 0;

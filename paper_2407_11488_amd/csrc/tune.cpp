@@ -51,7 +51,7 @@ static bool json_config(const JsonObj& o, conv2d_config* c)
 // source revision of the same (arch, shape) is used only when no current one
 // exists (every configuration is correct; it may no longer be the fastest).
 int cache_lookup(const std::string& path, const std::string& arch, const conv2d_shape& s,
-                 conv2d_config* c, double* ms)
+                 conv2d_config* c, double* ms, bool* stale)
 {
     std::ifstream f(path);
     if (!f) return fail(CONV2D_ENOTUNED, "no winners cache at " + path);
@@ -72,6 +72,33 @@ int cache_lookup(const std::string& path, const std::string& arch, const conv2d_
     if (!have_cur && !have_old) return fail(CONV2D_ENOTUNED, "shape not in winners cache");
     if (c) *c = have_cur ? cur : old;
     if (ms) *ms = have_cur ? cur_ms : old_ms;
+    if (stale) *stale = !have_cur;
+    return CONV2D_OK;
+}
+
+int cache_lookup_filter(const std::string& path, const std::string& arch, int fh, int fw,
+                        const conv2d_shape& prefer, conv2d_config* c)
+{
+    if (cache_lookup(path, arch, prefer, c, nullptr) == CONV2D_OK) return CONV2D_OK;
+    std::ifstream f(path);
+    if (!f) return fail(CONV2D_ENOTUNED, "no winners cache at " + path);
+    const std::string src = hex64(direct_source_hash());
+    bool have_cur = false, have_old = false;
+    conv2d_config cur{}, old{};
+    std::string line;
+    while (std::getline(f, line)) {
+        JsonObj o;
+        if (!json_parse_line(line, &o) || o.str["arch"] != arch) continue;
+        auto it = o.arr.find("shape");
+        if (it == o.arr.end() || it->second.size() != 4 || (int)it->second[2] != fh || (int)it->second[3] != fw)
+            continue;
+        conv2d_config cc;
+        if (!json_config(o, &cc)) continue;
+        if (o.str["src"] == src) { cur = cc; have_cur = true; }
+        else { old = cc; have_old = true; }
+    }
+    if (!have_cur && !have_old) return fail(CONV2D_ENOTUNED, "filter size not in winners cache");
+    *c = have_cur ? cur : old;
     return CONV2D_OK;
 }
 
@@ -227,6 +254,8 @@ public:
             n_flush_ = (512ull << 20) / 4;
             if (hipMalloc(&d_flush_, n_flush_ * 4) != hipSuccess)
                 return fail(CONV2D_ENOMEM, "tuner: flush buffer allocation failed");
+            rc = launch_fill_value(d_flush_, n_flush_, 0.0f, stream_);  // the flush reads zeros
+            if (rc) return rc;
         }
         rc = launch_fill_uniform(d_in_, n_in_, 1, 0, stream_);
         if (!rc) rc = launch_fill_uniform(d_f_, (size_t)s_.filt_h * s_.filt_w, 2, 0, stream_);
@@ -659,4 +688,35 @@ extern "C" int conv2d_cache_store(const char* path, const char* arch, conv2d_sha
         a = d.arch;
     }
     return cache_store(path ? path : winners_default_path(), a, s, *cfg, ms);
+}
+
+extern "C" int conv2d_benchmark(conv2d_shape s, const conv2d_config* cfg, int warmup, int reps, int flush_mall,
+                                double* median_ms, double* min_ms)
+{
+    clear_error();
+    if (!cfg) return fail(CONV2D_EINVAL, "cfg is NULL");
+    int rc = shape_check(s);
+    if (rc) return rc;
+    conv2d_tune_opts o;
+    conv2d_tune_defaults(&o);
+    o.flush_mall = flush_mall ? 1 : 0;
+    o.threads = 1;
+    GpuMeasurer m(s, o);
+    rc = m.init();
+    if (rc) return rc;
+    rc = conv2d_config_check(s, cfg, m.lds_limit());
+    if (rc) return rc;
+    std::vector<int> st;
+    double sec = 0;
+    rc = m.prepare({*cfg}, &st, &sec);
+    if (rc) return rc;
+    if (st[0] != kOk) return CONV2D_ECOMPILE;  // message left by the compiler
+    Record r;
+    rc = m.measure(*cfg, warmup < 0 ? 0 : warmup, reps < 1 ? 1 : reps, 0, &r);
+    if (rc) return rc;
+    if (r.status == kLaunch) return fail(CONV2D_ELAUNCH, "benchmark: launch failed");
+    if (r.status == kVerify) return fail(CONV2D_EVERIFY, "benchmark: output differs from the reference kernel");
+    if (median_ms) *median_ms = r.ms;
+    if (min_ms) *min_ms = r.ms_min;
+    return CONV2D_OK;
 }

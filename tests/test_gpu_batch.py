@@ -1,0 +1,129 @@
+"""GPU parity of the batched path (conv2d_batch_plan / conv2d_batch_run),
+through the C ABI: the 64-problem uneven workload against the FP64 oracle and
+bitwise against the plain path, graph replays, pointer changes, and errors."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests.gpu_util import TOL, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+C = pytest.importorskip("paper_2407_11488_amd")
+
+
+def _device_problem(torch, shape, p):
+    H, W, fh, fw = shape
+    n_in = (H + fh - 1) * (W + fw - 1)
+    inp = torch.empty((H + fh - 1, W + fw - 1), dtype=torch.float32, device="cuda")
+    f = torch.empty((fh, fw), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    C.conv2d_fill_uniform(inp.data_ptr(), n_in, datagen.SEED_BATCH_INPUT_BASE + p, 0, st)
+    C.conv2d_fill_uniform(f.data_ptr(), fh * fw, datagen.SEED_BATCH_FILTER_BASE + p, 0, st)
+    return inp, f
+
+
+@pytest.fixture(scope="module")
+def workload():
+    torch = torch_cuda()
+    shapes = datagen.batch_shapes()
+    ins, fs = zip(*[_device_problem(torch, s, p) for p, s in enumerate(shapes)])
+    torch.cuda.synchronize()
+    return shapes, list(ins), list(fs)
+
+
+def test_batch_uneven_workload_matches_oracle_and_plain(workload):
+    """64 problems, square outputs log-uniform in [256, 2048], filters from
+    {3, 5, 9, 17}: every output within tolerance of the FP64 oracle and bitwise
+    equal to a plain conv2d_run of the same problem."""
+    torch = torch_cuda()
+    shapes, ins, fs = workload
+    batch = C.Batch(shapes)
+    say(f"batch groups {batch.info}")
+    outs = [torch.full((H, W), float("nan"), device="cuda") for (H, W, _, _) in shapes]
+    batch(ins, fs, outs)
+    torch.cuda.synchronize()
+    for p, (H, W, fh, fw) in enumerate(shapes):
+        got = outs[p].cpu().numpy()
+        assert np.all(np.isfinite(got)), p
+        inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=datagen.SEED_BATCH_INPUT_BASE + p,
+                                      seed_f=datagen.SEED_BATCH_FILTER_BASE + p)
+        assert np.array_equal(ins[p].cpu().numpy().view(np.uint32), inp.view(np.uint32))
+        ref, s = oracle.conv2d_f64(inp, f)
+        err = oracle.normalized_error(got, ref, s)
+        assert err <= TOL, (p, err)
+        plain = C.conv2d(ins[p], fs[p])
+        torch.cuda.synchronize()
+        assert np.array_equal(plain.cpu().numpy().view(np.uint32), got.view(np.uint32)), p
+    batch.close()
+
+
+def test_graph_replays_and_pointer_changes(workload):
+    """The graph replayed several times, with eager work and synchronisation in
+    between, and with new output buffers (descriptor re-upload): every replay
+    equals the first result; the direct-launch path agrees."""
+    torch = torch_cuda()
+    shapes, ins, fs = workload
+    sel = list(range(0, 64, 4))
+    sub = [shapes[k] for k in sel]
+    batch = C.Batch(sub)
+    outs = [torch.full((H, W), float("nan"), device="cuda") for (H, W, _, _) in sub]
+    batch([ins[k] for k in sel], [fs[k] for k in sel], outs)
+    torch.cuda.synchronize()
+    first = [o.cpu().numpy().copy() for o in outs]
+    for rep in range(4):
+        say(f"replay {rep}")
+        for o in outs:
+            o.fill_(float("nan"))                        # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        if rep == 2:
+            outs = [torch.full((H, W), float("nan"), device="cuda") for (H, W, _, _) in sub]
+        batch([ins[k] for k in sel], [fs[k] for k in sel], outs)
+        torch.cuda.synchronize()
+        for a, o in zip(first, outs):
+            assert np.array_equal(a.view(np.uint32), o.cpu().numpy().view(np.uint32))
+        del junk
+    batch.close()
+    direct = C.Batch(sub, flags=C.CONV2D_BATCH_NO_GRAPH)
+    outs2 = direct([ins[k] for k in sel], [fs[k] for k in sel])
+    torch.cuda.synchronize()
+    for a, o in zip(first, outs2):
+        assert np.array_equal(a.view(np.uint32), o.cpu().numpy().view(np.uint32))
+    direct.close()
+
+
+def test_batch_edge_cases():
+    """One problem; tiny problems smaller than a tile; a rectangular filter."""
+    torch = torch_cuda()
+    shapes = [(1, 1, 3, 3), (2, 300, 5, 5), (77, 1, 17, 17), (33, 65, 3, 7), (40, 40, 3, 3)]
+    ins, fs = zip(*[_device_problem(torch, s, 50 + p) for p, s in enumerate(shapes)])
+    for sub in (shapes[:1], shapes):
+        b = C.Batch(sub)
+        outs = b(list(ins[:len(sub)]), list(fs[:len(sub)]))
+        torch.cuda.synchronize()
+        for p, (H, W, fh, fw) in enumerate(sub):
+            inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=datagen.SEED_BATCH_INPUT_BASE + 50 + p,
+                                          seed_f=datagen.SEED_BATCH_FILTER_BASE + 50 + p)
+            ref, s = oracle.conv2d_f64(inp, f)
+            assert oracle.normalized_error(outs[p].cpu().numpy(), ref, s) <= TOL
+        b.close()
+
+
+def test_batch_errors():
+    torch = torch_cuda()
+    with pytest.raises(C.Conv2dError):
+        C.conv2d_batch_plan([])
+    with pytest.raises(C.Conv2dError):
+        C.conv2d_batch_plan([(10, 10, 3, 3), (0, 10, 3, 3)])
+    b = C.conv2d_batch_plan([(10, 10, 3, 3)])
+    try:
+        inp = torch.zeros((12, 12), device="cuda")
+        f = torch.zeros((3, 3), device="cuda")
+        with pytest.raises(C.Conv2dError):
+            C.conv2d_batch_run(b, [inp.data_ptr()], [f.data_ptr()], [0])
+        with pytest.raises(C.Conv2dError):
+            C.conv2d_batch_run(b, [inp.data_ptr()], [f.data_ptr()], [inp.data_ptr()])
+    finally:
+        C.conv2d_batch_destroy(b)

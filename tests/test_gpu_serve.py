@@ -1,0 +1,115 @@
+"""GPU tests of the serving loop (conv2d_serve) through the C ABI: each result
+the same alone and in the mix, HBM-budget admission, the serial baseline, and
+argument errors."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests.gpu_util import TOL, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+C = pytest.importorskip("paper_2407_11488_amd")
+
+
+def small_trace(n=48, rate=20000.0, seed=11, lo=32, hi=384):
+    t = datagen.poisson_arrivals(rate, n / rate * 3, seed=seed)[:n]
+    sides = datagen.log_uniform_sides(seed + 1, len(t), lo, hi)
+    fs = datagen.filter_choices(seed + 1, len(t))
+    shapes = [(int(s), int(s) + (k % 3), int(f), int(f)) for k, (s, f) in enumerate(zip(sides, fs))]
+    seeds_in = [5000 + k for k in range(len(t))]
+    seeds_f = [6000 + k for k in range(len(t))]
+    return C.requests_array(t, shapes, seeds_in, seeds_f), shapes
+
+
+def _hip_runtime():
+    """The HIP runtime this process already uses (the one torch loaded)."""
+    with open("/proc/self/maps") as fh:
+        paths = sorted({ln.split()[-1] for ln in fh if "libamdhip64" in ln})
+    assert len(paths) == 1, paths
+    hip = ctypes.CDLL(paths[0])
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return hip
+
+
+def _copy_out(ptr, H, W):
+    torch = torch_cuda()
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    hip = _hip_runtime()
+    assert hip.hipMemcpy(out.data_ptr(), ptr, H * W * 4, 3) == 0  # device to device
+    return out
+
+
+def _plain(shape, seed_in, seed_f):
+    """The same request alone: device-generated data, one plain conv2d_run."""
+    torch = torch_cuda()
+    H, W, fh, fw = shape
+    inp = torch.empty((H + fh - 1, W + fw - 1), dtype=torch.float32, device="cuda")
+    f = torch.empty((fh, fw), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    C.conv2d_fill_uniform(inp.data_ptr(), inp.numel(), seed_in, 0, st)
+    C.conv2d_fill_uniform(f.data_ptr(), f.numel(), seed_f, 0, st)
+    out = C.conv2d(inp, f)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("serial", [0, 1])
+def test_results_same_alone_and_in_the_mix(serial):
+    reqs, shapes = small_trace()
+    o = C.conv2d_serve_defaults()
+    o.serial_plain = serial
+    o.streams = 3
+    o.max_batch = 16
+    say(f"serve {len(reqs)} requests serial={serial}")
+    rep, lat, outs = C.conv2d_serve(reqs, o, keep_outputs=True)
+    try:
+        assert rep.n_requests == len(reqs) and np.all(lat > 0)
+        if not serial:
+            assert rep.n_batches < len(reqs), "no request was batched with another"
+        for k, (H, W, fh, fw) in enumerate(shapes):
+            got = _copy_out(outs[k], H, W).cpu().numpy()
+            alone = _plain(shapes[k], int(reqs["seed_in"][k]), int(reqs["seed_f"][k])).cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), alone.view(np.uint32)), k
+            if k % 8 == 0:
+                inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=int(reqs["seed_in"][k]),
+                                              seed_f=int(reqs["seed_f"][k]))
+                ref, s = oracle.conv2d_f64(inp, f)
+                assert oracle.normalized_error(got, ref, s) <= TOL
+    finally:
+        C.conv2d_serve_free(outs)
+
+
+def test_budget_admission_bounds_memory():
+    reqs, shapes = small_trace(n=40, rate=1e6, seed=21, lo=200, hi=400)
+    need = [4 * ((H + fh - 1) * (W + fw - 1) + fh * fw + H * W) + 3 * 256 for (H, W, fh, fw) in shapes]
+    o = C.conv2d_serve_defaults()
+    o.hbm_budget = int(max(need) * 1.5)
+    o.streams = 2
+    rep, lat, _ = C.conv2d_serve(reqs, o)
+    say(f"tight budget: {rep.as_dict()}")
+    assert rep.n_requests == len(reqs)
+    assert rep.peak_bytes <= o.hbm_budget
+    assert rep.stalled_requests > 0
+
+
+def test_serve_argument_errors():
+    reqs, _ = small_trace(n=4)
+    o = C.conv2d_serve_defaults()
+    o.hbm_budget = 1 << 20
+    big = C.requests_array([0.0], [(1024, 1024, 17, 17)], [1], [2])
+    with pytest.raises(C.Conv2dError):
+        C.conv2d_serve(big, o)                       # alone above the budget
+    bad = reqs.copy()
+    bad["arrival_s"] = bad["arrival_s"][::-1]
+    if len(bad) > 1 and bad["arrival_s"][0] != bad["arrival_s"][-1]:
+        with pytest.raises(C.Conv2dError):
+            C.conv2d_serve(bad)                      # arrivals out of order
+    o = C.conv2d_serve_defaults()
+    o.streams = 0
+    with pytest.raises(C.Conv2dError):
+        C.conv2d_serve(reqs, o)

@@ -106,3 +106,49 @@ def test_emulated_kernel_exact(binaries, shape, tmp_path):
         assert np.array_equal(got.astype(np.float64), ref), f"config {cfg} differs from the oracle"
         n += 1
     assert n > 20
+
+
+BATCH_CONFIGS = [(16, 1, 1, 1, 0, 0, 1), (64, 1, 4, 4, 1, 0, 0), (32, 4, 2, 8, 0, 0, 1), (16, 16, 4, 1, 1, 0, 2),
+                 (128, 2, 8, 2, 1, 0, 1)]
+
+
+def build_batch(cfg, fh, fw):
+    bx, by, tx, ty, lds, fc, un = cfg
+    defs = dict(BX=bx, BY=by, TX=tx, TY=ty, USE_LDS=lds, FCONST=0, UNROLL=un, FH=fh, FW=fw, VIN=1, VOUT=1, BATCH=1)
+    src = open(KERNEL).read() + open(os.path.join(EMU, "emu_batch.cpp")).read() + \
+        open(os.path.join(EMU, "hip_emu.h")).read()
+    key = hashlib.sha1((src + repr(sorted(defs.items()))).encode()).hexdigest()[:16]
+    os.makedirs(BIN_DIR, exist_ok=True)
+    exe = os.path.join(BIN_DIR, f"emub_{key}")
+    if not os.path.exists(exe):
+        cmd = [CXX, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+               "-fno-omit-frame-pointer", *[f"-DCONV_{k}={v}" for k, v in defs.items()],
+               os.path.join(EMU, "emu_batch.cpp"), "-o", exe + ".tmp", "-lpthread"]
+        subprocess.run(cmd, check=True, capture_output=True)
+        os.replace(exe + ".tmp", exe)
+    return exe
+
+
+@pytest.mark.parametrize("fh,fw", [(3, 3), (5, 2)])
+def test_emulated_batch_kernel_exact(fh, fw, tmp_path):
+    """The persistent kernel over uneven images: every output of every image
+    written once and exact, for grids that are and are not multiples of 8."""
+    sizes = [(37, 45), (5, 130), (64, 64), (1, 1), (19, 7)]
+    probs = []
+    for k, (H, W) in enumerate(sizes):
+        inp, f = datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=100 + k, seed_f=200 + k)
+        inp.astype(np.float32).tofile(tmp_path / f"in{k}.f32")
+        f.astype(np.float32).tofile(tmp_path / f"f{k}.f32")
+        probs.append((H, W, oracle.conv2d_f64(inp, f)[0]))
+    with cf.ThreadPoolExecutor(os.cpu_count() or 4) as ex:
+        exes = list(ex.map(lambda c: build_batch(c, fh, fw), BATCH_CONFIGS))
+    args = [str(v) for H, W, _ in probs for v in (H, W)]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    for cfg, exe in zip(BATCH_CONFIGS, exes):
+        for grid in (8, 11, 24):
+            r = subprocess.run([exe, str(grid), str(tmp_path), str(len(probs)), *args], capture_output=True,
+                               text=True, env=env, timeout=300)
+            assert r.returncode == 0, r.stderr[-3000:]
+            for k, (H, W, ref) in enumerate(probs):
+                got = np.fromfile(tmp_path / f"out{k}.f32", np.float32).reshape(H, W)
+                assert np.array_equal(got.astype(np.float64), ref), (cfg, grid, k)
