@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--default-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="duration of the serving trace (batched and serial each); 0 skips serving")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, run plain copy/negate kernels over this many MiB "
                          "(calibration of the profiler's byte counters)")
@@ -152,6 +155,22 @@ def main():
             torch.neg(src, out=dst)       # reads n*4 bytes, writes n*4 bytes
         torch.cuda.synchronize()
         line["calibration"] = {"kernel": "torch.neg elementwise", "read_bytes": n * 4, "write_bytes": n * 4}
+    del d_in, d_out
+    torch.cuda.empty_cache()
+    from paper_2407_11488_amd import workloads
+    if not args.no_batch:
+        line["batch"] = workloads.batch_benchmark(reps=20)
+    if args.serve_seconds > 0:
+        sv = workloads.serve_benchmark(duration=args.serve_seconds, rates=(0.8,))
+        run = sv["runs"][0]
+        line["serving"] = {"workload": sv["workload"], "duration_s": sv["duration_s"],
+                           "rate_req_s": run["rate_req_s"], "serial_capacity_req_s": sv["serial_capacity_req_s"],
+                           "batched_capacity_req_s": sv["batched_capacity_req_s"],
+                           "p50_ms": run["batched"]["p50_ms"], "p99_ms": run["batched"]["p99_ms"],
+                           "req_per_s": run["batched"]["req_per_s"], "gflops": run["batched"]["gflops"],
+                           "mean_batch": run["batched"]["mean_batch"],
+                           "serial_p50_ms": run["serial"]["p50_ms"], "serial_p99_ms": run["serial"]["p99_ms"],
+                           "serial_req_per_s": run["serial"]["req_per_s"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -138,10 +138,9 @@ int batch_module_for_filter(const DeviceInfo& dev, int fh, int fw, conv2d_config
         cfg->filter_in_const = 0;
         clear_error();
     }
-    std::vector<char> code;
-    int rc = compile_direct(tuned_shape, *cfg, 1, 1, dev.arch, &code, nullptr, true);
-    if (rc) return rc;
-    return load_module(code, direct_kernel_name(tuned_shape, *cfg, true), m);
+    // The batched kernel stores with scalar writes (any row alignment); with
+    // a fully unrolled row loop that can spill, and the rolled loop is used.
+    return build_module(tuned_shape, cfg, 1, 1, dev.arch, true, true, m);
 }
 
 int launch_batch_kernel(const Module& m, const conv2d_config& cfg, int grid, const void* d_desc,

@@ -313,7 +313,10 @@ CONV_NAME(const ConvDesc* __restrict__ descs, const unsigned short* __restrict__
     const int count = q + (xcd < rem ? 1 : 0);
     for (int k = first; k < count; k += stride) {
         const int t = begin + k;
-        const ConvDesc* d = descs + owner[t];
+        // The owner is read with a 16-bit vector load (no 16-bit scalar load
+        // on gfx9); it is the same for every lane, and saying so keeps the
+        // descriptor, the filter taps and all addressing in scalar registers.
+        const ConvDesc* d = descs + __builtin_amdgcn_readfirstlane((int)owner[t]);
         const int lt = t - d->tile_begin;
         if ((unsigned)lt >= (unsigned)d->n_tiles)
             continue;  // inconsistent tables: skip rather than store out of range (uniform)

@@ -74,6 +74,11 @@ struct Module {
     size_t const_bytes = 0;
 };
 int load_module(const std::vector<char>& code, const std::string& kernel, Module* m);
+// Compiles and loads a configuration. With allow_fallback, a build whose
+// kernel spills to scratch (a fully or partly unrolled row loop can, for some
+// alignment classes) is replaced by the rolled loop (cfg->unroll becomes 1).
+int build_module(const conv2d_shape& s, conv2d_config* cfg, int vin, int vout, const std::string& arch, bool batch,
+                 bool allow_fallback, Module* m);
 void unload_module(Module* m);
 
 // ---------------------------------------------------------------- device

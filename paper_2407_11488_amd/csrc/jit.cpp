@@ -132,6 +132,28 @@ int load_module(const std::vector<char>& code, const std::string& kernel, Module
     return CONV2D_OK;
 }
 
+int build_module(const conv2d_shape& s, conv2d_config* cfg, int vin, int vout, const std::string& arch, bool batch,
+                 bool allow_fallback, Module* m)
+{
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        std::vector<char> code;
+        int rc = compile_direct(s, *cfg, vin, vout, arch, &code, nullptr, batch);
+        if (rc) return rc;
+        rc = load_module(code, direct_kernel_name(s, *cfg, batch), m);
+        if (rc) return rc;
+        if (!allow_fallback || cfg->unroll == 1) return CONV2D_OK;
+        int scratch = 0;
+        if (hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, m->fn) != hipSuccess) {
+            (void)hipGetLastError();
+            return CONV2D_OK;
+        }
+        if (scratch == 0) return CONV2D_OK;
+        unload_module(m);
+        cfg->unroll = 1;
+    }
+    return CONV2D_OK;
+}
+
 void unload_module(Module* m)
 {
     if (m && m->mod) hipModuleUnload(m->mod);

@@ -213,12 +213,16 @@ extern "C" int conv2d_geometry(conv2d_shape s, const conv2d_config* cfg, int* ti
 
 // ---------------------------------------------------------------- plan / run
 
-static int build_module(conv2d_plan_s* p, int vin, int vout, Module* m)
+// Builds the plan's module for an alignment class. A configuration the
+// library chose (tuned or default) falls back to the rolled row loop if this
+// alignment class makes it spill; a given or forced one is built as asked.
+// Only the unroll can change, which does not affect the launch geometry.
+static int build_module(conv2d_plan_s* p, int vin, int vout, Module* m, bool is_main)
 {
-    std::vector<char> code;
-    int rc = compile_direct(p->shape, p->cfg, vin, vout, p->arch, &code, nullptr);
-    if (rc) return rc;
-    return load_module(code, direct_kernel_name(p->shape, p->cfg), m);
+    conv2d_config c = p->cfg;
+    int rc = build_module(p->shape, &c, vin, vout, p->arch, false, p->source != 2, m);
+    if (rc == CONV2D_OK && is_main) p->cfg = c;
+    return rc;
 }
 
 extern "C" int conv2d_plan(conv2d_plan_t* plan, conv2d_shape s, const conv2d_config* cfg)
@@ -261,7 +265,7 @@ extern "C" int conv2d_plan(conv2d_plan_t* plan, conv2d_shape s, const conv2d_con
     if (rc) return rc;
     p->vin = vec_class((long long)s.out_w + s.filt_w - 1);
     p->vout = vec_class(s.out_w);
-    rc = build_module(p.get(), p->vin, p->vout, &p->main);
+    rc = build_module(p.get(), p->vin, p->vout, &p->main, true);
     if (rc) return rc;
     *plan = p.release();
     return CONV2D_OK;
@@ -312,7 +316,7 @@ extern "C" int conv2d_run(conv2d_plan_t plan, const float* d_in, const float* d_
     if (!aligned) {
         std::lock_guard<std::mutex> lk(plan->mu);
         if (!plan->unaligned.fn) {
-            rc = build_module(plan, 1, 1, &plan->unaligned);
+            rc = build_module(plan, 1, 1, &plan->unaligned, false);
             if (rc) return rc;
         }
         m = &plan->unaligned;

@@ -93,3 +93,6 @@ inline void emu_nontemporal_store(T v, T* p)
     *p = v;
 }
 #define __builtin_nontemporal_store(v, p) emu_nontemporal_store(v, p)
+
+// Every lane of a workgroup holds the same value wherever the kernels use it.
+inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
