@@ -42,6 +42,23 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_RECORD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                              "conv2d_direct_4096x4096_f17_traffic.json")
+
+
+def measured_traffic(C, plan):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    record, if it was taken on this kernel source and configuration; else None."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None, None
+    if rec.get("kernel_hash") != C.conv2d_kernel_hash() or list(rec.get("config", [])) != list(plan.config):
+        return None, None
+    return rec["traffic_bytes_per_launch"], os.path.basename(TRAFFIC_RECORD)
+
+
 def time_plan(torch, C, plan, d_in, d_f, d_out, steps, warmup, stream):
     """Average kernel time per step (ms) from HIP events on the launch stream,
     and the wall time of the timed region."""
@@ -110,14 +127,17 @@ def main():
     gflops = flops / (ms * 1e-3) / 1e9
     achieved_tflops = gflops / 1e3
 
+    traffic, traffic_src = measured_traffic(C, plan)
+    kname = "conv2d_direct_b{}x{}_t{}x{}_l{}c{}u{}_f{}x{}".format(*plan.config, FH, FW)
     roofline = {
         "bound": "alu",
         "achieved": round(achieved_tflops, 3),
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-        "traffic": None,
-        "kernel": "conv2d_direct",
+        "traffic": traffic,
+        "traffic_source": traffic_src,
+        "kernel": kname,
         "peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
         "frac_unpacked": round(achieved_tflops / PEAK_FP32_UNPACKED_TFLOPS, 4),
         "algorithmic_bytes_per_launch": 4 * (n_in + H * W + FH * FW),

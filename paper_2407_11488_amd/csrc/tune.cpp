@@ -311,8 +311,17 @@ public:
     }
 
 private:
+    // What conv2d_run enqueues: the filter copy into the module's constant
+    // array (filter_in_const = 1), then the kernel. The tuner times exactly
+    // this, so a constant-memory filter is charged for its copy.
     int launch(const Module& m, const conv2d_config& c)
     {
+        if (c.filter_in_const) {
+            if (!m.const_filter) return fail(CONV2D_ELAUNCH, "module has no conv_filter symbol");
+            if (hipMemcpyAsync(m.const_filter, d_f_, 4ull * s_.filt_h * s_.filt_w, hipMemcpyDeviceToDevice,
+                               stream_) != hipSuccess)
+                return fail(CONV2D_ELAUNCH, "filter copy failed");
+        }
         return launch_direct(m, s_, c, d_in_, d_f_, d_out_, stream_);
     }
 
@@ -321,9 +330,6 @@ private:
     {
         int rc = launch_fill_value(d_out_, n_out_, __builtin_nanf(""), stream_);
         if (rc) return rc;
-        if (c.filter_in_const)
-            CONV2D_HIP(hipMemcpyAsync(m.const_filter, d_f_, 4ull * s_.filt_h * s_.filt_w,
-                                      hipMemcpyDeviceToDevice, stream_));
         if (launch(m, c) != CONV2D_OK) {
             (void)hipGetLastError();
             r->status = kLaunch;
