@@ -70,6 +70,61 @@ def performance_portability(effs) -> float:
     return len(effs) / sum(1.0 / e for e in effs)
 
 
+def ffg_edges(times: dict, axes):
+    """Fitness flow graph (Section 4, "Tuning difficulty"): nodes are the
+    timed configurations; x -> y for every neighbour y of x with strictly
+    lower time. Neighbours differ in one parameter by one step of that
+    parameter's ordered value list (the paper does not define the
+    neighbourhood; this is the reading taken). Returns (nodes, edges) with
+    edges as (i, j) index pairs into the sorted node list."""
+    nodes = sorted(times)
+    index = {c: i for i, c in enumerate(nodes)}
+    edges = []
+    for c in nodes:
+        for k, values in enumerate(axes):
+            pos = values.index(c[k])
+            for q in (pos - 1, pos + 1):
+                if 0 <= q < len(values):
+                    n = c[:k] + (values[q],) + c[k + 1:]
+                    if n in index and times[n] < times[c]:
+                        edges.append((index[c], index[n]))
+    return nodes, edges
+
+
+def pagerank_dense(n: int, edges, damping: float = 0.85) -> np.ndarray:
+    """PageRank (Brin and Page 1998) by a direct linear solve: with M the
+    column-stochastic transition matrix (each node's out-edges weighted
+    equally; a node without out-edges links to every node), r solves
+    (I - d M) r = (1 - d)/n * 1. The damping 0.85 is the usual value (the
+    paper does not state one)."""
+    M = np.zeros((n, n))
+    out = [[] for _ in range(n)]
+    for i, j in edges:
+        out[i].append(j)
+    for i in range(n):
+        if out[i]:
+            for j in out[i]:
+                M[j, i] += 1.0 / len(out[i])
+        else:
+            M[:, i] = 1.0 / n
+    r = np.linalg.solve(np.eye(n) - damping * M, np.full(n, (1.0 - damping) / n))
+    return r / r.sum()
+
+
+def proportion_of_centrality(times: dict, axes, p: float, damping: float = 0.85) -> float:
+    """Eq. 1: the PageRank mass of the local minima whose time is at most
+    (1 + p) * best, over the mass of all local minima (nodes of the FFG with
+    no better neighbour). The paper writes "less than", but plots p = 0 as
+    the global optimum itself, so the bound is read as inclusive."""
+    nodes, edges = ffg_edges(times, axes)
+    r = pagerank_dense(len(nodes), edges, damping)
+    has_out = {i for i, _ in edges}
+    minima = [i for i in range(len(nodes)) if i not in has_out]
+    best = min(times.values())
+    good = [i for i in minima if times[nodes[i]] <= (1.0 + p) * best]
+    return float(sum(r[i] for i in good) / sum(r[i] for i in minima))
+
+
 def percentile_nearest_rank(values, p: float) -> float:
     v = np.sort(np.asarray(values, dtype=np.float64))
     if v.size == 0:

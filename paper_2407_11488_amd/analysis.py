@@ -134,3 +134,69 @@ def most_portable(dbs: dict):
         return None, {}
     c = max(sorted(t), key=lambda k: t[k]["pp"])
     return c, t[c]
+
+
+# ---------------------------------------------------------------- tuning difficulty
+
+SPACE_AXES = ((16, 32, 64, 128), (1, 2, 4, 8, 16), (1, 2, 4, 8), (1, 2, 4, 8), (0, 1), (0, 1))
+
+
+def fitness_flow_graph(times: dict, axes=SPACE_AXES):
+    """The fitness flow graph of Section 4: timed configurations as nodes and
+    an edge from each node to every neighbour with a strictly lower time.
+    Neighbours differ in one parameter by one step of its ordered value list.
+    Returns (nodes, out_lists)."""
+    nodes = sorted(times)
+    index = {c: i for i, c in enumerate(nodes)}
+    out = [[] for _ in nodes]
+    for i, c in enumerate(nodes):
+        t = times[c]
+        for k, values in enumerate(axes):
+            pos = values.index(c[k])
+            for q in (pos - 1, pos + 1):
+                if 0 <= q < len(values):
+                    j = index.get(c[:k] + (values[q],) + c[k + 1:])
+                    if j is not None and times[nodes[j]] < t:
+                        out[i].append(j)
+    return nodes, out
+
+
+def pagerank(out, damping: float = 0.85, tol: float = 1e-14, max_iter: int = 10000):
+    """PageRank by power iteration: a node spreads its rank equally over its
+    out-edges; nodes without out-edges spread theirs over every node."""
+    import numpy as np
+    n = len(out)
+    src = np.array([i for i, o in enumerate(out) for _ in o], dtype=np.int64)
+    dst = np.array([j for o in out for j in o], dtype=np.int64)
+    deg = np.array([len(o) for o in out], dtype=np.float64)
+    dangling = deg == 0
+    w = np.zeros(len(src)) if len(src) == 0 else 1.0 / deg[src]
+    r = np.full(n, 1.0 / n)
+    for _ in range(max_iter):
+        nxt = np.zeros(n)
+        np.add.at(nxt, dst, r[src] * w)
+        nxt = damping * (nxt + r[dangling].sum() / n) + (1.0 - damping) / n
+        nxt /= nxt.sum()
+        if np.abs(nxt - r).sum() < tol:
+            return nxt
+        r = nxt
+    return r
+
+
+def proportion_of_centrality(times: dict, ps=(0.0, 0.01, 0.02, 0.05, 0.10, 0.15), axes=SPACE_AXES,
+                             damping: float = 0.85) -> dict:
+    """Eq. 1 for each p: PageRank mass of the local minima within (1 + p) of
+    the best time, over the mass of all local minima."""
+    nodes, out = fitness_flow_graph(times, axes)
+    r = pagerank(out, damping)
+    minima = [i for i, o in enumerate(out) if not o]
+    best = min(times.values())
+    total = sum(r[i] for i in minima)
+    return {p: float(sum(r[i] for i in minima if times[nodes[i]] <= (1.0 + p) * best) / total) for p in ps}
+
+
+def base_space_times(db: str, shape, unroll: int = 1) -> dict:
+    """Times (ms) of the timed points of the base sweep (one unroll value),
+    keyed by the 6-parameter tuple."""
+    return {c[:6]: r["ms"] for c, r in load(db, shape).items()
+            if r.get("status") == "ok" and r.get("ms", 0) > 0 and c[6] == unroll}
