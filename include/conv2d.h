@@ -271,6 +271,12 @@ typedef struct conv2d_tune_opts {
     double tie_rel;            /* relative tie window for the winner (default 0.005) */
     int verbose;               /* 1: progress lines on stderr */
     int refine_unroll;         /* 1: also time the ten fastest points with the other unroll values */
+    int strategy;              /* 0: brute force over the space (default); 1: random-restart hill
+                                  climbing (one parameter one step per move; restart k starts at
+                                  the idx-th unevaluated point in enumeration order,
+                                  idx = splitmix64(seed, k) mod count), stopping at max_evals */
+    int max_evals;             /* local search budget in evaluations (default 100) */
+    uint64_t seed;             /* local search seed */
 } conv2d_tune_opts;
 
 typedef struct conv2d_tune_result {
@@ -289,6 +295,7 @@ typedef struct conv2d_tune_result {
     conv2d_config top[5];      /* fastest five, fastest first */
     double top_ms[5];
     double compile_s, measure_s; /* wall time of the compile and measure phases */
+    int evaluations;           /* configurations measured in this call (failures included) */
 } conv2d_tune_result;
 
 /* Defaults for every option. */

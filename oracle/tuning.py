@@ -125,6 +125,62 @@ def proportion_of_centrality(times: dict, axes, p: float, damping: float = 0.85)
     return float(sum(r[i] for i in good) / sum(r[i] for i in minima))
 
 
+def local_search(times: dict, legal: list, axes, max_evals: int, seed: int):
+    """Random-restart hill climbing as the tuner's local-search strategy
+    defines it, written plainly. times[c] is the time of configuration c, or
+    None for a point that fails. legal lists the points in enumeration order.
+    A walk evaluates every unevaluated neighbour (one parameter one step, in
+    axis order, the lower value first) and moves to the fastest while that
+    improves; restart k starts at the idx-th unevaluated point, idx =
+    splitmix64(seed, k) mod count (the counter form of SplitMix64). Returns
+    (best configuration, configurations in evaluation order)."""
+    from datagen import splitmix64
+    index = set(legal)
+    state, order = {}, []
+
+    def evaluate(cfgs):
+        for c in cfgs:
+            if len(order) >= max_evals:
+                return
+            state[c] = times[c]
+            order.append(c)
+
+    def neighbours(c):
+        out = []
+        for k, vals in enumerate(axes):
+            pos = list(vals).index(c[k])
+            for q in (pos - 1, pos + 1):
+                if 0 <= q < len(vals):
+                    n = c[:k] + (vals[q],) + c[k + 1:]
+                    if n in index:
+                        out.append(n)
+        return out
+
+    restart = 0
+    while len(order) < max_evals:
+        fresh = [c for c in legal if c not in state]
+        if not fresh:
+            break
+        z = int(splitmix64(seed, np.array([restart], dtype=np.uint64))[0])
+        restart += 1
+        cur = fresh[z % len(fresh)]
+        evaluate([cur])
+        if state.get(cur) is None:
+            continue
+        while len(order) < max_evals:
+            nb = neighbours(cur)
+            evaluate([n for n in nb if n not in state])
+            ok = [n for n in nb if state.get(n) is not None]
+            if not ok:
+                break
+            nxt = min(ok, key=lambda c: (state[c], c))
+            if not state[nxt] < state[cur]:
+                break
+            cur = nxt
+    ok = [c for c in state if state[c] is not None]
+    return min(ok, key=lambda c: (state[c], c)), order
+
+
 def percentile_nearest_rank(values, p: float) -> float:
     v = np.sort(np.asarray(values, dtype=np.float64))
     if v.size == 0:

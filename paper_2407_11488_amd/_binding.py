@@ -79,7 +79,7 @@ class TuneOpts(ctypes.Structure):
     _fields_ = [("winners_path", c_char_p), ("results_path", c_char_p), ("warmup", c_int), ("reps", c_int),
                 ("retime_reps", c_int), ("flush_mall", c_int), ("threads", c_int), ("unroll", c_int),
                 ("max_configs", c_int), ("tie_rel", c_double), ("verbose", c_int),
-                ("refine_unroll", c_int)]
+                ("refine_unroll", c_int), ("strategy", c_int), ("max_evals", c_int), ("seed", c_uint64)]
 
 
 class TuneResult(ctypes.Structure):
@@ -88,7 +88,7 @@ class TuneResult(ctypes.Structure):
                 ("impact", c_double), ("n_space", c_int), ("n_illegal", c_int), ("n_compile_fail", c_int),
                 ("n_launch_fail", c_int), ("n_verify_fail", c_int), ("n_timed", c_int), ("n_resumed", c_int),
                 ("default_rank", c_int), ("top", Config * 5), ("top_ms", c_double * 5),
-                ("compile_s", c_double), ("measure_s", c_double)]
+                ("compile_s", c_double), ("measure_s", c_double), ("evaluations", c_int)]
 
 
 COST_FN = ctypes.CFUNCTYPE(c_double, ctypes.POINTER(Config), c_void_p)

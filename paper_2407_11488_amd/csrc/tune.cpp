@@ -420,6 +420,128 @@ void load_results(const std::string& path, const std::string& arch, const conv2d
     }
 }
 
+// SplitMix64 output number k of stream `seed` (Steele, Lea and Flood 2014).
+uint64_t splitmix64(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Random-restart hill climbing over the legal points (a local-search
+// strategy in place of brute force, for shapes where a full sweep costs too
+// much). From a start point, all not-yet-evaluated neighbours (one parameter
+// moved one step along its ordered value list) are evaluated and the walk
+// moves to the fastest neighbour while that improves; at a local minimum it
+// restarts from the idx-th not-yet-evaluated point in enumeration order, with
+// idx = splitmix64(seed, restart) mod (number not yet evaluated). Stops after
+// max_evals evaluations (failures count). Ties go to the smallest tuple.
+int local_search(const conv2d_shape& s, const conv2d_tune_opts& o, Measurer* meas, conv2d_tune_result* res,
+                 const std::vector<conv2d_config>& legal)
+{
+    const double t0 = now_s();
+    std::map<std::string, int> index;
+    for (size_t i = 0; i < legal.size(); ++i) index[config_str(legal[i])] = (int)i;
+    std::vector<int> state(legal.size(), 0);  // 0 not evaluated, 1 ok, -1 failed
+    std::vector<double> ms(legal.size(), 0.0);
+    int evals = 0;
+    const int budget = o.max_evals > 0 ? o.max_evals : 100;
+
+    auto evaluate = [&](const std::vector<int>& ids) -> int {
+        std::vector<conv2d_config> cfgs;
+        for (int i : ids) cfgs.push_back(legal[i]);
+        std::vector<int> st;
+        double sec = 0;
+        int rc = meas->prepare(cfgs, &st, &sec);
+        if (rc) return rc;
+        res->compile_s += sec;
+        for (size_t k = 0; k < ids.size() && evals < budget; ++k) {
+            const int i = ids[k];
+            Record r;
+            r.c = legal[i];
+            if (st[k] != kOk) r.status = st[k];
+            else {
+                rc = meas->measure(legal[i], o.warmup, o.reps, 0, &r);
+                if (rc) return rc;
+            }
+            ++evals;
+            state[i] = r.status == kOk ? 1 : -1;
+            ms[i] = r.ms;
+            if (r.status == kCompile) res->n_compile_fail++;
+            else if (r.status == kLaunch) res->n_launch_fail++;
+            else if (r.status == kVerify) res->n_verify_fail++;
+            if (o.results_path && *o.results_path) append_line(o.results_path, result_line(meas->arch(), s, r));
+        }
+        return CONV2D_OK;
+    };
+    auto neighbours = [&](int i) {
+        static const std::vector<std::vector<int>> axes = {
+            {16, 32, 64, 128}, {1, 2, 4, 8, 16}, {1, 2, 4, 8}, {1, 2, 4, 8}, {0, 1}, {0, 1}};
+        std::vector<int> out;
+        const conv2d_config& c = legal[i];
+        int v[6] = {c.block_x, c.block_y, c.tile_x, c.tile_y, c.use_lds, c.filter_in_const};
+        for (int k = 0; k < 6; ++k) {
+            const auto& vals = axes[k];
+            const int pos = (int)(std::find(vals.begin(), vals.end(), v[k]) - vals.begin());
+            for (int q : {pos - 1, pos + 1}) {
+                if (q < 0 || q >= (int)vals.size()) continue;
+                int w[6];
+                std::copy(v, v + 6, w);
+                w[k] = vals[q];
+                conv2d_config n{w[0], w[1], w[2], w[3], w[4], w[5], c.unroll};
+                auto it = index.find(config_str(n));
+                if (it != index.end()) out.push_back(it->second);
+            }
+        }
+        return out;
+    };
+    auto better = [&](int a, int b) {  // a strictly preferable to b
+        return ms[a] < ms[b] || (ms[a] == ms[b] && config_less(legal[a], legal[b]));
+    };
+
+    uint64_t restart = 0;
+    while (evals < budget) {
+        std::vector<int> fresh;
+        for (size_t i = 0; i < legal.size(); ++i)
+            if (!state[i]) fresh.push_back((int)i);
+        if (fresh.empty()) break;
+        int cur = fresh[splitmix64((uint64_t)o.seed, restart++) % fresh.size()];
+        int rc = evaluate({cur});
+        if (rc) return rc;
+        if (state[cur] != 1) continue;
+        while (evals < budget) {
+            std::vector<int> todo;
+            const std::vector<int> nb = neighbours(cur);
+            for (int n : nb)
+                if (!state[n]) todo.push_back(n);
+            rc = evaluate(todo);
+            if (rc) return rc;
+            int next = -1;
+            for (int n : nb)
+                if (state[n] == 1 && (next < 0 || better(n, next))) next = n;
+            if (next < 0 || !(ms[next] < ms[cur])) break;
+            cur = next;
+        }
+    }
+    int best = -1;
+    for (size_t i = 0; i < legal.size(); ++i)
+        if (state[i] == 1 && (best < 0 || better((int)i, best))) best = (int)i;
+    res->n_timed = 0;
+    for (int st : state) res->n_timed += (st == 1);
+    res->measure_s = now_s() - t0;
+    if (best < 0) return fail(CONV2D_EVERIFY, "local search: no configuration compiled, ran and verified");
+    res->best = legal[best];
+    res->best_ms = ms[best];
+    res->best_gflops = gflops_of(s, ms[best]);
+    res->evaluations = evals;
+    if (o.winners_path && *o.winners_path) {
+        int rc = cache_store(o.winners_path, meas->arch(), s, legal[best], ms[best]);
+        if (rc) return rc;
+    }
+    return CONV2D_OK;
+}
+
 int tune_core(const conv2d_shape& s, const conv2d_tune_opts& o, Measurer* meas, conv2d_tune_result* res)
 {
     *res = conv2d_tune_result{};
@@ -440,6 +562,7 @@ int tune_core(const conv2d_shape& s, const conv2d_tune_opts& o, Measurer* meas, 
     }
     clear_error();
     if (o.max_configs > 0 && (int)legal.size() > o.max_configs) legal.resize(o.max_configs);
+    if (o.strategy == 1) return local_search(s, o, meas, res, legal);
     std::vector<conv2d_config> candidates = legal;
     if (!default_in_space && conv2d_config_check(s, &dflt, meas->lds_limit()) == CONV2D_OK)
         candidates.push_back(dflt);  // timed for tuned/default, not eligible as winner
@@ -566,6 +689,7 @@ int tune_core(const conv2d_shape& s, const conv2d_tune_opts& o, Measurer* meas, 
         std::sort(eligible.begin(), eligible.end(), by_time);
     }
     res->measure_s = now_s() - t0;
+    res->evaluations = (int)(candidates.size()) - res->n_resumed;
 
     // Winner: lowest time; ties within tie_rel go to the smallest tuple.
     const double fastest = eligible[0].ms;
@@ -635,6 +759,9 @@ extern "C" void conv2d_tune_defaults(conv2d_tune_opts* o)
     o->unroll = 1;
     o->max_configs = 0;
     o->tie_rel = 0.005;
+    o->strategy = 0;
+    o->max_evals = 100;
+    o->seed = 1;
 }
 
 extern "C" int conv2d_tune(conv2d_shape s, const conv2d_tune_opts* opts, conv2d_tune_result* res)

@@ -63,8 +63,13 @@ def tune_one(shape, a, results_path):
     o.flush_mall = 0 if a.no_flush else 1
     o.unroll, o.max_configs, o.threads, o.verbose = a.unroll, a.max_configs, a.threads, 1
     o.refine_unroll = 0 if a.no_refine_unroll else 1
+    if a.strategy == "local":
+        o.strategy, o.max_evals, o.seed = 1, a.max_evals, a.seed
     r = B.conv2d_tune(B.shape(*shape), o)
-    return report(shape, r)
+    rep = report(shape, r)
+    rep["strategy"] = a.strategy
+    rep["evaluations"] = r.evaluations
+    return rep
 
 
 def emit(rep, path):
@@ -92,6 +97,10 @@ def main(argv=None) -> int:
     ap.add_argument("--no-refine-unroll", action="store_true")
     ap.add_argument("--max-configs", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--strategy", choices=("brute", "local"), default="brute",
+                    help="brute: the whole space; local: random-restart hill climbing")
+    ap.add_argument("--max-evals", type=int, default=100)
+    ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
 

@@ -209,3 +209,32 @@ def test_cache_prefers_current_kernel_source(tmp_path):
     assert c.tuple() == (32, 2, 4, 4, 1, 1, 2) and ms == 0.5
     assert C.conv2d_cache_lookup(str(p), "gfx942", s) is None
     assert C.conv2d_cache_lookup(str(p), "gfx950", C.shape(100, 200, 3, 3)) is None
+
+
+@pytest.mark.parametrize("seed,budget", [(1, 60), (7, 200), (123, 1300)])
+def test_local_search_follows_its_definition(tmp_path, seed, budget):
+    """The tuner's local-search strategy (synthetic cost) evaluates exactly the
+    points, in exactly the order, of the plain replay in the oracle, and
+    returns the same best point; with a budget above the space it reaches
+    the global optimum."""
+    import json as _json
+    rng = np.random.default_rng(seed)
+    s = C.shape(4096, 4096, 17, 17)
+    legal = C.conv2d_space(s, 1, 0)
+    table = {c: float(rng.lognormal(0, 0.4)) for c in legal}
+    fails = {c for k, c in enumerate(legal) if k % 53 == 0}
+    cost = {c: (C.CONV2D_ECOMPILE if c in fails else t) for c, t in table.items()}
+    o = C.conv2d_tune_defaults()
+    o.strategy, o.max_evals, o.seed = 1, budget, seed
+    res_path = tmp_path / "r.jsonl"
+    o.results_path = str(res_path).encode()
+    r = C.conv2d_tune_synthetic(s, lambda c: cost[c], o)
+    order = [tuple(_json.loads(x)["config"]) for x in open(res_path)]
+    axes = [list(v) for _, v in ospace.AXES]
+    best, want = otune.local_search({c: (None if c in fails else t) for c, t in table.items()}, legal, axes,
+                                    budget, seed)
+    assert order == want
+    assert r.best.tuple() == best and r.evaluations == len(want)
+    if budget >= len(legal):
+        ok = {c: t for c, t in table.items() if c not in fails}
+        assert best == min(ok, key=lambda c: (ok[c], c))
