@@ -1,4 +1,5 @@
-"""CPU oracle for the direct 2D convolution — TEST INFRASTRUCTURE ONLY.
+"""CPU oracles for the direct 2D convolution and the hotspot stencil — TEST
+INFRASTRUCTURE ONLY.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The HIP library never calls it, and the
@@ -7,6 +8,8 @@ convolution arithmetic).
 
 * ``conv2d_f64`` / ``conv2d_points_f64`` / ``conv2d_rows_f64``: the plain FP64
   definition of the convolution (see ``conv2d_oracle.c``), parallel over rows.
+* ``hotspot_f64``: the hotspot thermal stencil (see ``hotspot_oracle.c``), FP64
+  explicit steps from FP32 inputs.
 * ``oracle.tuning``: the tuner's statistics (tuning impact, median, top-k,
   application efficiency, performance portability), written from their
   definitions in the paper's Section 4.
@@ -22,7 +25,7 @@ import time
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "conv2d_oracle.c")
+_SRCS = [os.path.join(_HERE, "conv2d_oracle.c"), os.path.join(_HERE, "hotspot_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle_conv2d.so")
 
 CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
@@ -33,7 +36,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc; returns the library path."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
+        subprocess.run(["gcc", *CFLAGS, *_SRCS, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -44,7 +47,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(p) for p in _SRCS):
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         fp, dp, lp = (ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double),
@@ -56,6 +59,9 @@ def _load():
         for fn in (lib.oracle_conv2d_f64, lib.oracle_conv2d_points_f64, lib.oracle_conv2d_rows_f64):
             fn.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
+        D = ctypes.c_double
+        lib.oracle_hotspot_f64.argtypes = [fp, fp, L, L, L, D, D, D, D, D, dp]
+        lib.oracle_hotspot_f64.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -147,3 +153,19 @@ def time_conv2d(inp, filt, repeats: int = 1):
         conv2d_f64(inp, filt, with_abs=False)
         best = min(best, time.perf_counter() - t0)
     return best
+
+
+def hotspot_f64(temp, power, steps: int, cc: float, gx: float, gy: float, gz: float, t_amb: float):
+    """The hotspot grid after ``steps`` explicit steps (FP64 result) from FP32
+    ``temp`` and ``power`` (rows x cols); coefficients as in hotspot_oracle.c."""
+    temp = np.ascontiguousarray(temp, dtype=np.float32)
+    power = np.ascontiguousarray(power, dtype=np.float32)
+    if temp.ndim != 2 or temp.shape != power.shape:
+        raise ValueError("temp and power must be 2-D arrays of one shape")
+    rows, cols = temp.shape
+    out = np.empty((rows, cols), np.float64)
+    rc = _load().oracle_hotspot_f64(_fptr(temp), _fptr(power), rows, cols, int(steps), float(cc), float(gx),
+                                    float(gy), float(gz), float(t_amb), _dptr(out))
+    if rc != 0:
+        raise ValueError("oracle_hotspot_f64 rejected its arguments")
+    return out
