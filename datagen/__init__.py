@@ -160,3 +160,43 @@ def serving_requests(rate_hz: float, duration_s: float, lo: int = 128, hi: int =
     sides = log_uniform_sides(seed + 7919, len(t), lo, hi)
     fs = filter_choices(seed + 7919, len(t))
     return t, [(int(s), int(s), int(f), int(f)) for s, f in zip(sides, fs)]
+
+
+# ---------------------------------------------------------------- hotspot workload
+# A square silicon chip split into rows x cols cells (the compact thermal RC
+# model's setting): side, thickness, conductivity and volumetric heat capacity
+# of silicon, ambient, and a peak power density.
+CHIP_SIDE_M = 0.016
+CHIP_THICKNESS_M = 0.0005
+K_SILICON = 100.0          # W / (m K)
+CV_SILICON = 1.75e6        # J / (m^3 K)
+T_AMBIENT_K = 318.15
+PEAK_POWER_W_M2 = 3.0e6
+SEED_HOTSPOT_TEMP = 71
+SEED_HOTSPOT_POWER = 72
+
+
+def hotspot_chip(rows: int, cols: int, stability: float = 0.25):
+    """(cc, gx, gy, gz, t_amb, p_max) of the chip workload: conductances G =
+    k A / d between neighbouring cell centres (A = thickness x cell side,
+    d = the other side) and through the thickness to the ambient (A = cell
+    area, d = thickness); the time step is `stability` times the explicit
+    step's stability limit C / (2 gx + 2 gy + gz), so cc = dt / C =
+    stability / (2 gx + 2 gy + gz); p_max is the peak power of one cell."""
+    w, h, t = CHIP_SIDE_M / cols, CHIP_SIDE_M / rows, CHIP_THICKNESS_M
+    gx = K_SILICON * t * h / w
+    gy = K_SILICON * t * w / h
+    gz = K_SILICON * w * h / t
+    cc = stability / (2 * gx + 2 * gy + gz)
+    return cc, gx, gy, gz, T_AMBIENT_K, PEAK_POWER_W_M2 * w * h
+
+
+def hotspot_problem(rows: int, cols: int, seed_t: int = SEED_HOTSPOT_TEMP, seed_p: int = SEED_HOTSPOT_POWER):
+    """FP32 (temp, power) grids and the FP32-rounded coefficients
+    (cc, gx, gy, gz, t_amb) of the chip workload: temperatures
+    t_amb + 30 K * u, powers p_max * u^2 (few hot cells), u uniform in [0, 1)."""
+    cc, gx, gy, gz, t_amb, p_max = hotspot_chip(rows, cols)
+    temp = (t_amb + 30.0 * unit_float(seed_t, rows * cols)).astype(np.float32).reshape(rows, cols)
+    power = (p_max * unit_float(seed_p, rows * cols) ** 2).astype(np.float32).reshape(rows, cols)
+    coeffs = tuple(float(np.float32(v)) for v in (cc, gx, gy, gz, t_amb))
+    return temp, power, coeffs

@@ -32,3 +32,37 @@ def product():
 def restricted():
     """Tuples with block_x * block_y <= 1024, in product order."""
     return [c for c in product() if c[0] * c[1] <= MAX_THREADS]
+
+
+# The hotspot space: the MI355X version of Table 1's hotspot parameters
+# (block sizes for wave64, per-thread tiles, temporal tiling factor, step-loop
+# unroll, power staging), restricted to 64..1024 threads, a region of
+# (block_y*tile_y) x (block_x*tile_x) cells larger than twice the temporal
+# factor along both axes (a non-empty output tile), and two LDS buffers of
+# rows x (cols + 1) floats within 160 KiB (never binding here: at most 16,384
+# cells per region, 131,200 bytes).
+HOTSPOT_AXES = (
+    ("block_x", (16, 32, 64, 128, 256)),
+    ("block_y", (1, 2, 4, 8, 16)),
+    ("tile_x", (1, 2, 4)),
+    ("tile_y", (1, 2, 4)),
+    ("temporal", (1, 2, 3, 4, 6, 8)),
+    ("unroll_t", (0, 1)),
+    ("sh_power", (0, 1)),
+)
+HOTSPOT_LDS_LIMIT = 163840
+
+
+def hotspot_restricted():
+    out = []
+    for c in itertools.product(*(vals for _, vals in HOTSPOT_AXES)):
+        bx, by, tx, ty, tt = c[:5]
+        rows, cols = by * ty, bx * tx
+        if not 64 <= bx * by <= MAX_THREADS:
+            continue
+        if rows <= 2 * tt or cols <= 2 * tt:
+            continue
+        if 2 * rows * (cols + 1) * 4 > HOTSPOT_LDS_LIMIT:
+            continue
+        out.append(c)
+    return out

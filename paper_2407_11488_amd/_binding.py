@@ -272,7 +272,7 @@ def conv2d_benchmark(s: Shape, cfg, warmup: int = 2, reps: int = 20, flush_mall:
     return med.value, mn.value
 
 
-CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK = 1, 2
+CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK, CONV2D_BATCH_PER_GROUP = 1, 2, 4
 
 for _name, (_res, _args) in {
     "conv2d_batch_plan": (c_int, [P(c_void_p), c_int, P(Shape), c_int]),
@@ -388,3 +388,141 @@ def conv2d_serve(reqs, opts: ServeOpts | None = None, keep_outputs: bool = False
 def conv2d_serve_free(outputs) -> None:
     arr = (c_void_p * len(outputs))(*outputs)
     lib.conv2d_serve_free(arr, len(outputs))
+
+
+# ---------------------------------------------------------------- hotspot stencil (hotspot.h)
+
+class HotspotConfig(ctypes.Structure):
+    _fields_ = [("block_x", c_int), ("block_y", c_int), ("tile_x", c_int), ("tile_y", c_int),
+                ("temporal", c_int), ("unroll_t", c_int), ("sh_power", c_int)]
+
+    def tuple(self):
+        return tuple(getattr(self, f) for f, _ in self._fields_)
+
+    def __repr__(self):
+        return "HotspotConfig(" + ",".join(str(v) for v in self.tuple()) + ")"
+
+
+class HotspotShape(ctypes.Structure):
+    _fields_ = [("rows", c_int), ("cols", c_int)]
+
+
+class HotspotCoeffs(ctypes.Structure):
+    _fields_ = [("cc", ctypes.c_float), ("gx", ctypes.c_float), ("gy", ctypes.c_float), ("gz", ctypes.c_float),
+                ("t_amb", ctypes.c_float)]
+
+
+class HotspotTuneOpts(ctypes.Structure):
+    _fields_ = [("winners_path", c_char_p), ("results_path", c_char_p), ("warmup", c_int), ("reps", c_int),
+                ("retime_reps", c_int), ("flush_mall", c_int), ("threads", c_int), ("max_configs", c_int),
+                ("tie_rel", c_double), ("verbose", c_int)]
+
+
+class HotspotTuneResult(ctypes.Structure):
+    _fields_ = [("best", HotspotConfig), ("best_ms", c_double), ("default_ms", c_double), ("median_ms", c_double),
+                ("best_gflops", c_double), ("median_gflops", c_double), ("default_gflops", c_double),
+                ("impact", c_double), ("n_space", c_int), ("n_illegal", c_int), ("n_compile_fail", c_int),
+                ("n_launch_fail", c_int), ("n_verify_fail", c_int), ("n_timed", c_int), ("n_resumed", c_int),
+                ("default_rank", c_int), ("top", HotspotConfig * 5), ("top_ms", c_double * 5),
+                ("compile_s", c_double), ("measure_s", c_double)]
+
+
+_HS_SIGS = {
+    "hotspot_default_config": (None, [P(HotspotConfig)]),
+    "hotspot_lds_bytes": (c_int, [P(HotspotConfig)]),
+    "hotspot_config_check": (c_int, [HotspotShape, P(HotspotConfig), c_int]),
+    "hotspot_space": (c_int, [HotspotShape, c_int, P(HotspotConfig), c_int]),
+    "hotspot_compile": (c_int, [P(HotspotConfig), c_char_p, c_int]),
+    "hotspot_plan": (c_int, [P(c_void_p), HotspotShape, P(HotspotConfig)]),
+    "hotspot_plan_config": (c_int, [c_void_p, P(HotspotConfig), P(c_int)]),
+    "hotspot_run": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, HotspotCoeffs, c_void_p]),
+    "hotspot_destroy": (None, [c_void_p]),
+    "hotspot_reference": (c_int, [HotspotShape, c_void_p, c_void_p, c_void_p, c_void_p, c_int, HotspotCoeffs,
+                                  c_void_p]),
+    "hotspot_tune_defaults": (None, [P(HotspotTuneOpts)]),
+    "hotspot_tune": (c_int, [HotspotShape, c_int, P(HotspotTuneOpts), P(HotspotTuneResult)]),
+}
+for _name, (_res, _args) in _HS_SIGS.items():
+    _fn = getattr(lib, _name)
+    _fn.restype, _fn.argtypes = _res, _args
+
+
+def hotspot_config(*vals) -> HotspotConfig:
+    if len(vals) == 1 and isinstance(vals[0], (tuple, list, HotspotConfig)):
+        vals = tuple(vals[0].tuple() if isinstance(vals[0], HotspotConfig) else vals[0])
+    return HotspotConfig(*[int(v) for v in vals])
+
+
+def hotspot_shape(rows, cols) -> HotspotShape:
+    return HotspotShape(int(rows), int(cols))
+
+
+def hotspot_coeffs(cc, gx, gy, gz, t_amb) -> HotspotCoeffs:
+    return HotspotCoeffs(float(cc), float(gx), float(gy), float(gz), float(t_amb))
+
+
+def hotspot_default_config() -> HotspotConfig:
+    c = HotspotConfig()
+    lib.hotspot_default_config(ctypes.byref(c))
+    return c
+
+
+def hotspot_lds_bytes(cfg) -> int:
+    return check(lib.hotspot_lds_bytes(ctypes.byref(hotspot_config(cfg))), "hotspot_lds_bytes")
+
+
+def hotspot_config_check(s: HotspotShape, cfg, lds_limit: int = 0) -> int:
+    return lib.hotspot_config_check(s, ctypes.byref(hotspot_config(cfg)), lds_limit)
+
+
+def hotspot_space(s: HotspotShape, lds_limit: int = 0):
+    n = check(lib.hotspot_space(s, lds_limit, None, 0), "hotspot_space")
+    arr = (HotspotConfig * max(n, 1))()
+    lib.hotspot_space(s, lds_limit, arr, n)
+    return [arr[k].tuple() for k in range(n)]
+
+
+def hotspot_compile(cfg) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    check(lib.hotspot_compile(ctypes.byref(hotspot_config(cfg)), buf, 4096), "hotspot_compile")
+    return buf.value.decode()
+
+
+def hotspot_plan(s: HotspotShape, cfg=None) -> int:
+    h = c_void_p()
+    check(lib.hotspot_plan(ctypes.byref(h), s, None if cfg is None else ctypes.byref(hotspot_config(cfg))),
+          "hotspot_plan")
+    return h.value
+
+
+def hotspot_plan_config(plan: int):
+    c, tuned = HotspotConfig(), c_int()
+    check(lib.hotspot_plan_config(plan, ctypes.byref(c), ctypes.byref(tuned)), "hotspot_plan_config")
+    return c.tuple(), tuned.value
+
+
+def hotspot_run(plan: int, d_temp: int, d_power: int, d_out: int, d_work, steps: int, k: HotspotCoeffs,
+                stream: int = 0) -> None:
+    check(lib.hotspot_run(plan, d_temp, d_power, d_out, d_work, int(steps), k, stream), "hotspot_run")
+
+
+def hotspot_destroy(plan: int) -> None:
+    lib.hotspot_destroy(plan)
+
+
+def hotspot_reference(s: HotspotShape, d_temp: int, d_power: int, d_out: int, d_work, steps: int,
+                      k: HotspotCoeffs, stream: int = 0) -> None:
+    check(lib.hotspot_reference(s, d_temp, d_power, d_out, d_work, int(steps), k, stream), "hotspot_reference")
+
+
+def hotspot_tune_defaults() -> HotspotTuneOpts:
+    o = HotspotTuneOpts()
+    lib.hotspot_tune_defaults(ctypes.byref(o))
+    return o
+
+
+def hotspot_tune(s: HotspotShape, steps: int, opts: HotspotTuneOpts | None = None) -> HotspotTuneResult:
+    r = HotspotTuneResult()
+    check(lib.hotspot_tune(s, int(steps), None if opts is None else ctypes.byref(opts), ctypes.byref(r)),
+          "hotspot_tune")
+    return r

@@ -119,3 +119,58 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Hotspot:
+    """A compiled hotspot configuration for one rows x cols grid (the tuned
+    winner of the hotspot winners cache when one exists, else the default)."""
+
+    def __init__(self, rows, cols, config=None):
+        self.shape = B.hotspot_shape(rows, cols)
+        self.handle = B.hotspot_plan(self.shape, config)
+        self.config, tuned = B.hotspot_plan_config(self.handle)
+        self.source = "given" if config is not None else ("tuned" if tuned else "default")
+        self._work = None
+
+    def __call__(self, temp, power, steps, coeffs, out=None, stream=None):
+        """The grid after `steps` steps; coeffs = (cc, gx, gy, gz, t_amb)."""
+        torch = _torch()
+        shp = (self.shape.rows, self.shape.cols)
+        _check_tensor(temp, "temp", shp)
+        _check_tensor(power, "power", shp)
+        if out is None:
+            out = torch.empty(shp, dtype=torch.float32, device=temp.device)
+        _check_tensor(out, "out", shp)
+        work = 0
+        if steps > self.config[4]:
+            if self._work is None or self._work.device != temp.device:
+                self._work = torch.empty(shp, dtype=torch.float32, device=temp.device)
+            work = self._work.data_ptr()
+        B.hotspot_run(self.handle, temp.data_ptr(), power.data_ptr(), out.data_ptr(), work, steps,
+                      B.hotspot_coeffs(*coeffs), _stream(stream))
+        return out
+
+    def close(self):
+        if self.handle:
+            B.hotspot_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hotspot_reference(temp, power, steps, coeffs, out=None, stream=None):
+    """The library's one-step-per-launch hotspot reference."""
+    torch = _torch()
+    rows, cols = temp.shape
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.float32, device=temp.device)
+    # torch's caching allocator keeps the work buffer's memory for this
+    # stream until the stream has passed the launches
+    work = torch.empty((rows, cols), dtype=torch.float32, device=temp.device) if steps > 1 else None
+    B.hotspot_reference(B.hotspot_shape(rows, cols), temp.data_ptr(), power.data_ptr(), out.data_ptr(),
+                        0 if work is None else work.data_ptr(), steps, B.hotspot_coeffs(*coeffs), _stream(stream))
+    return out

@@ -26,13 +26,16 @@ ARCH = os.environ.get("CONV2D_BUILD_ARCH", "gfx950")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 CXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Kernel sources the library compiles at run time with hiprtc (embedded into
+# it), not at build time.
+RUNTIME_SOURCES = {"conv2d_direct.hip", "hotspot.hip"}
 COMMON = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 
 
 def _sources():
     cpp = sorted(f for f in os.listdir(CSRC) if f.endswith(".cpp"))
-    hip = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip") and f != "conv2d_direct.hip")
+    hip = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip") and f not in RUNTIME_SOURCES)
     return cpp, hip
 
 
@@ -50,9 +53,9 @@ def _compile(src: str) -> str:
 
 
 def _check_direct_kernel():
-    """Compiles the run-time-compiled kernel source through the library's own
-    hiprtc path (no GPU needed) for the default and a register-tiled
-    configuration, so that an error in the kernel source fails the build."""
+    """Compiles the run-time-compiled kernel sources through the library's own
+    hiprtc path (no GPU needed), each for two configurations, so that an error
+    in a kernel source fails the build."""
     import ctypes
 
     class Shape(ctypes.Structure):
@@ -62,12 +65,20 @@ def _check_direct_kernel():
         _fields_ = [(n, ctypes.c_int) for n in ("block_x", "block_y", "tile_x", "tile_y", "use_lds",
                                                  "filter_in_const", "unroll")]
 
+    class HotspotConfig(ctypes.Structure):
+        _fields_ = [(n, ctypes.c_int) for n in ("block_x", "block_y", "tile_x", "tile_y", "temporal",
+                                                 "unroll_t", "sh_power")]
+
     lib = ctypes.CDLL(LIB)
     lib.conv2d_last_error.restype = ctypes.c_char_p
     for cfg, vin, vout in (((16, 16, 1, 1, 1, 1, 1), 4, 4), ((64, 1, 8, 8, 0, 0, 1), 1, 2)):
         rc = lib.conv2d_compile(Shape(64, 64, 17, 17), ctypes.byref(Config(*cfg)), vin, vout, None, 0)
         if rc != 0:
             raise RuntimeError(f"kernel source check failed for {cfg}: {lib.conv2d_last_error().decode()}")
+    for cfg in ((32, 8, 1, 1, 1, 1, 1), (64, 4, 2, 4, 4, 0, 0)):
+        rc = lib.hotspot_compile(ctypes.byref(HotspotConfig(*cfg)), None, 0)
+        if rc != 0:
+            raise RuntimeError(f"hotspot source check failed for {cfg}: {lib.conv2d_last_error().decode()}")
 
 
 def build(verbose: bool = False) -> str:

@@ -1,7 +1,7 @@
 // Fixed kernels compiled into the library for gfx950: the plain reference
-// convolution the tuner verifies against, the seeded input generator, a
-// bitwise comparison, fills, and the last-level-cache flush used between
-// timed launches.
+// convolution and hotspot step the tuners verify against, the seeded input
+// generator, a bitwise comparison, fills, and the last-level-cache flush used
+// between timed launches.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -96,6 +96,31 @@ __global__ void flush_kernel(const float4* __restrict__ d, size_t n4, float* __r
     if (acc != 0.0f) sink[threadIdx.x] = acc;
 }
 
+// One explicit hotspot step, one cell per thread (the hotspot tuner's
+// reference). The cell's expression and its order are those of the tunable
+// hotspot kernel; a neighbour outside the grid is the cell itself.
+__global__ void __launch_bounds__(256)
+hotspot_reference_kernel(const float* __restrict__ tin, const float* __restrict__ power, float* __restrict__ tout,
+                         int rows, int cols, float cc, float gx, float gy, float gz, float t_amb)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)rows * cols) return;
+    const int r = (int)(idx / cols);
+    const int c = (int)(idx - (long long)r * cols);
+    const float t = tin[idx];
+    const float north = r > 0 ? tin[idx - cols] : t;
+    const float south = r < rows - 1 ? tin[idx + cols] : t;
+    const float west = c > 0 ? tin[idx - 1] : t;
+    const float east = c < cols - 1 ? tin[idx + 1] : t;
+    const float t2 = t + t;
+    const float lap_y = (north + south) - t2;
+    const float lap_x = (west + east) - t2;
+    float flow = __builtin_fmaf(lap_y, gy, power[idx]);
+    flow = __builtin_fmaf(lap_x, gx, flow);
+    flow = __builtin_fmaf(t_amb - t, gz, flow);
+    tout[idx] = __builtin_fmaf(flow, cc, t);
+}
+
 int grid_for(size_t n, int block)
 {
     size_t g = (n + block - 1) / block;
@@ -113,6 +138,18 @@ int launch_reference(const conv2d_shape& s, const float* d_in, const float* d_f,
     if (blocks > 0x7fffffffll) return fail(CONV2D_EINVAL, "reference: image too large");
     hipLaunchKernelGGL(reference_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, d_in, d_f,
                        d_out, s.out_h, s.out_w, s.filt_h, s.filt_w);
+    CONV2D_HIP(hipGetLastError());
+    return CONV2D_OK;
+}
+
+int launch_hotspot_reference_step(int rows, int cols, const float* d_in, const float* d_power, float* d_out,
+                                  float cc, float gx, float gy, float gz, float t_amb, hipStream_t stream)
+{
+    const long long n = (long long)rows * cols;
+    const long long blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffll) return fail(CONV2D_EINVAL, "hotspot reference: grid too large");
+    hipLaunchKernelGGL(hotspot_reference_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, d_in, d_power, d_out,
+                       rows, cols, cc, gx, gy, gz, t_amb);
     CONV2D_HIP(hipGetLastError());
     return CONV2D_OK;
 }

@@ -42,28 +42,18 @@
 //    round-robin) receives one contiguous run of tiles, keeping vertically
 //    adjacent tiles, which share FH-1 input rows, in the same L2.
 
+#ifndef CONV_BATCH
+#define CONV_BATCH 0
+#endif
+
+#if CONV_BATCH != 2
 #ifndef CONV_BX
 #error "CONV_BX must be defined"
+#endif
 #endif
 
 #ifndef CONV_NAME
 #define CONV_NAME conv2d_direct
-#endif
-
-#define NT (CONV_BX * CONV_BY)
-#define WIN (CONV_TX + CONV_FW - 1)
-#define NROWS (CONV_TY + CONV_FH - 1)
-
-#if CONV_UNROLL == 0
-#define ROW_UNROLL _Pragma("unroll")
-#elif CONV_UNROLL == 1
-#define ROW_UNROLL _Pragma("unroll 1")
-#elif CONV_UNROLL == 2
-#define ROW_UNROLL _Pragma("unroll 2")
-#elif CONV_UNROLL == 4
-#define ROW_UNROLL _Pragma("unroll 4")
-#else
-#define ROW_UNROLL _Pragma("unroll 8")
 #endif
 
 typedef unsigned int u32;
@@ -72,31 +62,43 @@ typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-#define GCD4(t) (((t) % 4 == 0) ? 4 : (((t) % 2 == 0) ? 2 : 1))
-#define MIN_(a, b) ((a) < (b) ? (a) : (b))
+static constexpr int gcd4(int t) { return (t % 4 == 0) ? 4 : ((t % 2 == 0) ? 2 : 1); }
+static constexpr int min_(int a, int b) { return a < b ? a : b; }
 
-// Vector width of a thread's window loads. The window starts at a multiple
-// of TX: from global memory it is aligned to min(gcd(TX, 4), VIN) elements,
-// from LDS (pitch a multiple of 4) to gcd(TX, 4). The register window is
-// padded to a whole number of those vectors.
-#if CONV_USE_LDS
-#define WVEC GCD4(CONV_TX)
-#else
-#define WVEC MIN_(GCD4(CONV_TX), CONV_VIN)
-#endif
-#define WIN_PAD (((WIN + WVEC - 1) / WVEC) * WVEC)
-// Output store width.
-#define SVEC MIN_(GCD4(CONV_TX), CONV_VOUT)
+// Derived sizes of one configuration (filter FH x FW, workgroup BX x BY
+// threads, TX x TY outputs per thread, LDS staging on/off, row-loop unroll,
+// input/output vector widths).
+template <int FH, int FW, int BX, int BY, int TX, int TY, int LDS, int UNROLL, int VIN, int VOUT>
+struct Geo {
+    static constexpr int NT = BX * BY;
+    static constexpr int WIN = TX + FW - 1;      // input values a thread's row window needs
+    static constexpr int NROWS = TY + FH - 1;    // input rows a thread walks
+    // Vector width of a thread's window loads. The window starts at a
+    // multiple of TX: from global memory it is aligned to min(gcd(TX, 4), VIN)
+    // elements, from LDS (pitch a multiple of 4) to gcd(TX, 4). The register
+    // window is padded to a whole number of those vectors.
+    static constexpr int WVEC = LDS ? gcd4(TX) : min_(gcd4(TX), VIN);
+    static constexpr int WIN_PAD = ((WIN + WVEC - 1) / WVEC) * WVEC;
+    static constexpr int SVEC = min_(gcd4(TX), VOUT);   // output store width
+    // Input halo tile of one workgroup in LDS, rows x pitch floats. The pitch
+    // is padded to a multiple of 4 (aligned ds_read_b128) plus 4 when it would
+    // otherwise be a multiple of 32 banks' worth, to spread the rows a wave
+    // reads over banks.
+    static constexpr int LDS_ROWS = BY * TY + FH - 1;
+    static constexpr int LDS_COLS = BX * TX + FW - 1;
+    static constexpr int LDS_CHUNKS = (LDS_COLS + VIN - 1) / VIN;
+    static constexpr int LDS_PITCH0 = ((LDS_CHUNKS * VIN + 3) / 4) * 4;
+    static constexpr int LDS_PITCH = (LDS_PITCH0 % 32 == 0) ? LDS_PITCH0 + 4 : LDS_PITCH0;
+    static constexpr int LDS_FLOATS = LDS ? LDS_ROWS * LDS_PITCH : 4;
+    static constexpr int ROW_UNROLL = UNROLL == 0 ? NROWS : UNROLL;   // 0 = the whole row loop
+};
 
+// Filter taps: the module's __constant__ copy, or the filter pointer.
 #if CONV_FCONST
 __constant__ float conv_filter[CONV_FH * CONV_FW];
-#define TAP(i, j) conv_filter[(i) * CONV_FW + (j)]
+#define TAPS conv_filter
 #else
-#define TAP(i, j) filt[(i) * CONV_FW + (j)]
-#endif
-
-#ifndef CONV_BATCH
-#define CONV_BATCH 0
+#define TAPS filt
 #endif
 
 static __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, u32 bytes)
@@ -154,86 +156,70 @@ static __device__ __forceinline__ int xcd_remap(int id, int n_tiles)
 {
     const int q = n_tiles >> 3, rem = n_tiles & 7;
     const int xcd = id & 7, k = id >> 3;
-    return xcd * q + MIN_(xcd, rem) + k;
+    return xcd * q + min_(xcd, rem) + k;
 }
-
-#if CONV_USE_LDS
-// Input halo tile of one workgroup, rows x pitch floats. The pitch is padded
-// to a multiple of 4 (aligned ds_read_b128) plus 4 when it would otherwise be
-// a multiple of 32 banks' worth, to spread the rows a wave reads over banks.
-#define LDS_ROWS (CONV_BY * CONV_TY + CONV_FH - 1)
-#define LDS_COLS (CONV_BX * CONV_TX + CONV_FW - 1)
-#define LDS_CHUNKS ((LDS_COLS + CONV_VIN - 1) / CONV_VIN)
-#define LDS_PITCH0 (((LDS_CHUNKS * CONV_VIN + 3) / 4) * 4)
-#define LDS_PITCH ((LDS_PITCH0 % 32 == 0) ? LDS_PITCH0 + 4 : LDS_PITCH0)
-#define LDS_FLOATS (LDS_ROWS * LDS_PITCH)
-#else
-#define LDS_FLOATS 4
-#endif
 
 // One output tile of (BY*TY) x (BX*TX) at tile coordinates (tile_y, tile_x)
 // of an image. Every thread of the workgroup calls it (the LDS variant
 // contains a barrier). `lds` is the workgroup's LDS tile.
+template <int FH, int FW, int BX, int BY, int TX, int TY, int LDS, int UNROLL, int VIN, int VOUT>
 static __device__ __forceinline__ void conv_tile(const float* __restrict__ in, const float* __restrict__ filt,
                                                  float* __restrict__ out, int H, int W, u32 in_bytes,
                                                  int tile_x, int tile_y, float* __restrict__ lds)
 {
-    const int lx = (int)threadIdx.x % CONV_BX;
-    const int ly = (int)threadIdx.x / CONV_BX;
-    const int x0 = tile_x * (CONV_BX * CONV_TX) + lx * CONV_TX;
-    const int y0 = tile_y * (CONV_BY * CONV_TY) + ly * CONV_TY;
-    const u32 P = (u32)W + (CONV_FW - 1);
+    using G = Geo<FH, FW, BX, BY, TX, TY, LDS, UNROLL, VIN, VOUT>;
+    const int lx = (int)threadIdx.x % BX;
+    const int ly = (int)threadIdx.x / BX;
+    const int x0 = tile_x * (BX * TX) + lx * TX;
+    const int y0 = tile_y * (BY * TY) + ly * TY;
+    const u32 P = (u32)W + (FW - 1);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(in, in_bytes);
 
-#if CONV_USE_LDS
-    {
-        const u32 gx0 = (u32)tile_x * (CONV_BX * CONV_TX);
-        const u32 gy0 = (u32)tile_y * (CONV_BY * CONV_TY);
-        for (int c = (int)threadIdx.x; c < LDS_ROWS * LDS_CHUNKS; c += NT) {
-            const int rr = c / LDS_CHUNKS;
-            const int cc = (c - rr * LDS_CHUNKS) * CONV_VIN;
-            float v[CONV_VIN];
-            buffer_row<CONV_VIN, CONV_VIN>(v, rs, ((gy0 + rr) * P + gx0 + cc) * 4u);
+    const float* lbase = lds;
+    if constexpr (LDS) {
+        const u32 gx0 = (u32)tile_x * (BX * TX);
+        const u32 gy0 = (u32)tile_y * (BY * TY);
+        for (int c = (int)threadIdx.x; c < G::LDS_ROWS * G::LDS_CHUNKS; c += G::NT) {
+            const int rr = c / G::LDS_CHUNKS;
+            const int cc = (c - rr * G::LDS_CHUNKS) * VIN;
+            float v[VIN];
+            buffer_row<VIN, VIN>(v, rs, ((gy0 + rr) * P + gx0 + cc) * 4u);
 #pragma unroll
-            for (int m = 0; m < CONV_VIN; ++m)
-                lds[rr * LDS_PITCH + cc + m] = v[m];
+            for (int m = 0; m < VIN; ++m)
+                lds[rr * G::LDS_PITCH + cc + m] = v[m];
         }
+        __syncthreads();
+        lbase = lds + (ly * TY) * G::LDS_PITCH + lx * TX;
     }
-    __syncthreads();
-    const float* lbase = lds + (ly * CONV_TY) * LDS_PITCH + lx * CONV_TX;
-#endif
 
     if (x0 >= W || y0 >= H)
         return;
 
-    float acc[CONV_TY][CONV_TX];
+    float acc[TY][TX];
 #pragma unroll
-    for (int o = 0; o < CONV_TY; ++o)
+    for (int o = 0; o < TY; ++o)
 #pragma unroll
-        for (int k = 0; k < CONV_TX; ++k)
+        for (int k = 0; k < TX; ++k)
             acc[o][k] = 0.0f;
 
-#if !CONV_USE_LDS
     const u32 off0 = ((u32)y0 * P + (u32)x0) * 4u;
-#endif
 
-    ROW_UNROLL
-    for (int r = 0; r < NROWS; ++r) {
-        float w[WIN_PAD];
-#if CONV_USE_LDS
-        lds_row<WVEC, WIN_PAD>(w, lbase + r * LDS_PITCH);
-#else
-        buffer_row<WVEC, WIN_PAD>(w, rs, off0 + (u32)r * P * 4u);
-#endif
+#pragma unroll G::ROW_UNROLL
+    for (int r = 0; r < G::NROWS; ++r) {
+        float w[G::WIN_PAD];
+        if constexpr (LDS)
+            lds_row<G::WVEC, G::WIN_PAD>(w, lbase + r * G::LDS_PITCH);
+        else
+            buffer_row<G::WVEC, G::WIN_PAD>(w, rs, off0 + (u32)r * P * 4u);
 #pragma unroll
-        for (int o = 0; o < CONV_TY; ++o) {
+        for (int o = 0; o < TY; ++o) {
             const int i = r - o;
-            if (i >= 0 && i < CONV_FH) {
+            if (i >= 0 && i < FH) {
 #pragma unroll
-                for (int j = 0; j < CONV_FW; ++j) {
-                    const float fv = TAP(i, j);
+                for (int j = 0; j < FW; ++j) {
+                    const float fv = TAPS[i * FW + j];
 #pragma unroll
-                    for (int k = 0; k < CONV_TX; ++k)
+                    for (int k = 0; k < TX; ++k)
                         acc[o][k] = __builtin_fmaf(w[k + j], fv, acc[o][k]);
                 }
             }
@@ -241,17 +227,17 @@ static __device__ __forceinline__ void conv_tile(const float* __restrict__ in, c
     }
 
 #pragma unroll
-    for (int o = 0; o < CONV_TY; ++o) {
+    for (int o = 0; o < TY; ++o) {
         const int y = y0 + o;
         if (y < H) {
             float* orow = out + (size_t)y * (size_t)W + x0;
-            if (x0 + CONV_TX <= W) {
+            if (x0 + TX <= W) {
 #pragma unroll
-                for (int k = 0; k < CONV_TX; k += SVEC) {
-                    if constexpr (SVEC == 4) {
+                for (int k = 0; k < TX; k += G::SVEC) {
+                    if constexpr (G::SVEC == 4) {
                         f32x4 v = {acc[o][k], acc[o][k + 1], acc[o][k + 2], acc[o][k + 3]};
                         __builtin_nontemporal_store(v, (f32x4*)(orow + k));
-                    } else if constexpr (SVEC == 2) {
+                    } else if constexpr (G::SVEC == 2) {
                         f32x2 v = {acc[o][k], acc[o][k + 1]};
                         __builtin_nontemporal_store(v, (f32x2*)(orow + k));
                     } else {
@@ -260,7 +246,7 @@ static __device__ __forceinline__ void conv_tile(const float* __restrict__ in, c
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < CONV_TX; ++k)
+                for (int k = 0; k < TX; ++k)
                     if (x0 + k < W)
                         orow[k] = acc[o][k];
             }
@@ -268,21 +254,23 @@ static __device__ __forceinline__ void conv_tile(const float* __restrict__ in, c
     }
 }
 
-#if !CONV_BATCH
+#if CONV_BATCH == 0
 // One image: one workgroup per tile, tiles_x * tiles_y = n_tiles workgroups.
-extern "C" __global__ void __launch_bounds__(NT)
+using G1 = Geo<CONV_FH, CONV_FW, CONV_BX, CONV_BY, CONV_TX, CONV_TY, CONV_USE_LDS, CONV_UNROLL, CONV_VIN, CONV_VOUT>;
+extern "C" __global__ void __launch_bounds__(G1::NT)
 CONV_NAME(const float* __restrict__ in, const float* __restrict__ filt,
           float* __restrict__ out, int H, int W, int tiles_x, int n_tiles, u32 in_bytes)
 {
-    __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
+    __shared__ __attribute__((aligned(16))) float lds[G1::LDS_FLOATS];
     const int t = xcd_remap((int)blockIdx.x, n_tiles);
     const int tile_y = t / tiles_x;
     const int tile_x = t - tile_y * tiles_x;
-    conv_tile(in, filt, out, H, W, in_bytes, tile_x, tile_y, lds);
+    conv_tile<CONV_FH, CONV_FW, CONV_BX, CONV_BY, CONV_TX, CONV_TY, CONV_USE_LDS, CONV_UNROLL, CONV_VIN, CONV_VOUT>(
+        in, filt, out, H, W, in_bytes, tile_x, tile_y, lds);
 }
 #else
 #if CONV_FCONST
-#error "the batched kernel reads each problem's own filter through its pointer"
+#error "the batched kernels read each problem's own filter through its pointer"
 #endif
 // One problem of a batch, as the host library lays it out in device memory.
 struct ConvDesc {
@@ -291,42 +279,126 @@ struct ConvDesc {
     float* out;
     int H, W;
     int tiles_x;
-    int tile_begin;   // first tile of this problem in the group's tile list
+    int tile_begin;   // first tile of this problem in the tile list
     u32 in_bytes;
     int n_tiles;      // tiles of this problem
+    int group;        // filter group (multi-filter kernel)
+    int pad_;
 };
 
+// The descriptor of tile t. The owner is read with a 16-bit vector load (no
+// 16-bit scalar load on gfx9); it is the same for every lane, and saying so
+// keeps the descriptor, the filter taps and all addressing in scalar registers.
+static __device__ __forceinline__ const ConvDesc* tile_desc(const ConvDesc* __restrict__ descs,
+                                                            const unsigned short* __restrict__ owner, int t)
+{
+    return descs + __builtin_amdgcn_readfirstlane((int)owner[t]);
+}
+
+#if CONV_BATCH == 1
 // Many images with the same filter size: a persistent grid (at least 8
 // workgroups) walks the group's tile list. The tiles of XCD x (= workgroup id
 // mod 8) form one contiguous range, shared out by stride among that XCD's
 // workgroups; owner[t] names the problem of tile t.
-extern "C" __global__ void __launch_bounds__(NT)
+using G1 = Geo<CONV_FH, CONV_FW, CONV_BX, CONV_BY, CONV_TX, CONV_TY, CONV_USE_LDS, CONV_UNROLL, CONV_VIN, CONV_VOUT>;
+extern "C" __global__ void __launch_bounds__(G1::NT)
 CONV_NAME(const ConvDesc* __restrict__ descs, const unsigned short* __restrict__ owner, int total_tiles)
 {
-    __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
+    __shared__ __attribute__((aligned(16))) float lds[G1::LDS_FLOATS];
     const int G = (int)gridDim.x;
     const int xcd = (int)blockIdx.x & 7;
     const int first = (int)blockIdx.x >> 3;
     const int stride = (G - xcd + 7) >> 3;
     const int q = total_tiles >> 3, rem = total_tiles & 7;
-    const int begin = xcd * q + MIN_(xcd, rem);
+    const int begin = xcd * q + min_(xcd, rem);
     const int count = q + (xcd < rem ? 1 : 0);
     for (int k = first; k < count; k += stride) {
         const int t = begin + k;
-        // The owner is read with a 16-bit vector load (no 16-bit scalar load
-        // on gfx9); it is the same for every lane, and saying so keeps the
-        // descriptor, the filter taps and all addressing in scalar registers.
-        const ConvDesc* d = descs + __builtin_amdgcn_readfirstlane((int)owner[t]);
+        const ConvDesc* d = tile_desc(descs, owner, t);
         const int lt = t - d->tile_begin;
         if ((unsigned)lt >= (unsigned)d->n_tiles)
             continue;  // inconsistent tables: skip rather than store out of range (uniform)
         const int tile_y = lt / d->tiles_x;
         const int tile_x = lt - tile_y * d->tiles_x;
-#if CONV_USE_LDS
-        if (k != first)
+        if (CONV_USE_LDS && k != first)
             __syncthreads();  // every thread is done with the previous tile's LDS
-#endif
-        conv_tile(d->in, d->filt, d->out, d->H, d->W, d->in_bytes, tile_x, tile_y, lds);
+        conv_tile<CONV_FH, CONV_FW, CONV_BX, CONV_BY, CONV_TX, CONV_TY, CONV_USE_LDS, CONV_UNROLL, CONV_VIN, CONV_VOUT>(
+            d->in, d->filt, d->out, d->H, d->W, d->in_bytes, tile_x, tile_y, lds);
     }
 }
+#else
+// Many images with several filter sizes in one persistent kernel.
+//   CONV_NT      threads per workgroup, shared by every group
+//   CONV_GROUPS  one G(k, FH, FW, BX, BY, TX, TY, LDS, UNROLL) per filter
+//                group k = 0, 1, ..., with BX * BY = CONV_NT
+// The tile list holds every group's tiles, costliest group first. A
+// workgroup starts at tile blockIdx.x and then takes the next unclaimed tile
+// from counters[0] (claimed one tile ahead, so the atomic's latency hides
+// behind the current tile), until the list is exhausted; the last workgroup
+// to finish (counted in counters[1]) sets both counters back to 0 for the
+// next launch. Input and output rows are accessed a float at a time (any
+// width, any alignment).
+#define G(k, fh, fw, bx, by, tx, ty, lds, unr) \
+    static_assert((bx) * (by) == CONV_NT, "every group of the multi-filter kernel has CONV_NT threads");
+CONV_GROUPS
+#undef G
+
+static constexpr int lds_floats_max()
+{
+    int m = 4;
+#define G(k, fh, fw, bx, by, tx, ty, lds, unr) \
+    m = m > Geo<fh, fw, bx, by, tx, ty, lds, unr, 1, 1>::LDS_FLOATS ? m : Geo<fh, fw, bx, by, tx, ty, lds, unr, 1, 1>::LDS_FLOATS;
+    CONV_GROUPS
+#undef G
+    return m;
+}
+
+extern "C" __global__ void __launch_bounds__(CONV_NT)
+CONV_NAME(const ConvDesc* __restrict__ descs, const unsigned short* __restrict__ owner, int total_tiles,
+          int* __restrict__ counters)
+{
+    __shared__ __attribute__((aligned(16))) float lds[lds_floats_max()];
+    __shared__ int next_tile[2];
+    int t = (int)blockIdx.x;
+    int parity = 0;
+    while (t < total_tiles) {
+        int claimed = 0;
+        if (threadIdx.x == 0)
+            claimed = (int)gridDim.x + atomicAdd(&counters[0], 1);
+        const ConvDesc* d = tile_desc(descs, owner, t);
+        const int lt = t - d->tile_begin;
+        if ((unsigned)lt < (unsigned)d->n_tiles) {   // else inconsistent tables: skip (uniform)
+            const int tile_y = lt / d->tiles_x;
+            const int tile_x = lt - tile_y * d->tiles_x;
+            switch (__builtin_amdgcn_readfirstlane(d->group)) {
+#define G(k, fh, fw, bx, by, tx, ty, lds_, unr) \
+            case k: \
+                conv_tile<fh, fw, bx, by, tx, ty, lds_, unr, 1, 1>(d->in, d->filt, d->out, d->H, d->W, d->in_bytes, \
+                                                                  tile_x, tile_y, lds); \
+                break;
+                CONV_GROUPS
+#undef G
+            default:
+                break;
+            }
+        }
+        // One barrier per tile: it publishes the next tile and tells every
+        // thread that the LDS tile is free again. The two slots alternate, so
+        // a slot is rewritten only after every thread has passed the barrier
+        // that follows its last read.
+        if (threadIdx.x == 0)
+            next_tile[parity] = claimed;
+        __syncthreads();
+        t = next_tile[parity];
+        parity ^= 1;
+    }
+    if (threadIdx.x == 0) {
+        if (atomicAdd(&counters[1], 1) == (int)gridDim.x - 1) {
+            // Every other workgroup has finished claiming tiles.
+            atomicExch(&counters[0], 0);
+            atomicExch(&counters[1], 0);
+        }
+    }
+}
+#endif
 #endif

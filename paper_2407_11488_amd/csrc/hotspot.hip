@@ -1,0 +1,188 @@
+// Hotspot thermal stencil for gfx950 (CDNA4) with temporal tiling, one
+// tunable configuration per compilation (the paper's hotspot kernel and its
+// tunable parameters, Section 5 and Table 1; the computation is the compact
+// thermal RC model of a chip, Huang et al., HotSpot, IEEE TVLSI 2006).
+//
+// One explicit step on a rows x cols grid of temperatures T and powers P:
+//   T'[r][c] = T + cc * (P + (T[r-1][c] + T[r+1][c] - 2T) * gy
+//                          + (T[r][c-1] + T[r][c+1] - 2T) * gx
+//                          + (t_amb - T) * gz)
+// where a neighbour outside the grid is the cell itself. Every cell is
+// evaluated by the same FP32 expression in the same order (two sums of
+// neighbours, then four fused multiply-adds), so every configuration returns
+// the same bits.
+//
+// Compile-time parameters (-D):
+//   HS_BX, HS_BY   workgroup shape in threads (block_size_x / block_size_y)
+//   HS_TX, HS_TY   cells per thread along x and y (tile_size_x / _y)
+//   HS_TT          temporal tiling factor: steps per launch (at most)
+//   HS_UNROLL_T    1: rolled step loop; 0: fully unrolled (loop_unroll_factor_t)
+//   HS_SH_POWER    1: each thread keeps its cells' power on chip for all steps;
+//                  0: power is read from global memory at every step (sh_power)
+//   HS_NAME        kernel symbol
+//
+// Design (MI355X): a workgroup owns a region of (BY*TY) x (BX*TX) cells, its
+// output tile plus a halo of TT cells on every side; neighbouring regions
+// overlap by 2*TT. Each thread keeps its TY x TX cells in VGPRs through all
+// steps. Per step it publishes them to one of two LDS buffers, waits once, and
+// reads from LDS only the ring of neighbours that belong to other threads.
+// After s steps the cells at distance >= s from the region's edge are exact;
+// after the launch's steps (<= TT) the inner tile is stored. The grid edge is
+// handled by coordinates, never by reading outside the grid.
+
+#ifndef HS_BX
+#error "HS_BX must be defined"
+#endif
+#ifndef HS_NAME
+#define HS_NAME hotspot_step
+#endif
+
+#define HS_NT (HS_BX * HS_BY)
+#define RH (HS_BY * HS_TY)   // region rows
+#define RW (HS_BX * HS_TX)   // region columns
+#define OH (RH - 2 * HS_TT)  // output tile rows
+#define OW (RW - 2 * HS_TT)  // output tile columns
+#define LDS_PITCH (RW + 1)   // odd pitch: a wave's column reads spread over the banks
+
+#if OH < 1 || OW < 1
+#error "the region must be larger than twice the temporal tiling factor"
+#endif
+
+static __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Workgroup id -> tile id: XCD x (= id mod 8) gets one contiguous run of
+// tiles, so neighbouring tiles, which share halo cells, meet in one L2.
+static __device__ __forceinline__ int xcd_remap(int id, int n_tiles)
+{
+    const int q = n_tiles >> 3, rem = n_tiles & 7;
+    const int xcd = id & 7, k = id >> 3;
+    return xcd * q + (xcd < rem ? xcd : rem) + k;
+}
+
+static __device__ __forceinline__ float cell_step(float t, float north, float south, float west, float east, float p,
+                                                  float cc, float gx, float gy, float gz, float t_amb)
+{
+    const float t2 = t + t;
+    const float lap_y = (north + south) - t2;
+    const float lap_x = (west + east) - t2;
+    float flow = __builtin_fmaf(lap_y, gy, p);
+    flow = __builtin_fmaf(lap_x, gx, flow);
+    flow = __builtin_fmaf(t_amb - t, gz, flow);
+    return __builtin_fmaf(flow, cc, t);
+}
+
+// The launch's steps over the thread's cells v (in place). EDGE = false when
+// the workgroup's whole region lies inside the grid: no cell then needs the
+// grid-edge rule, and the per-cell coordinate tests disappear.
+template <bool EDGE>
+static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const float (&pw)[HS_TY][HS_TX],
+                                                 float (*buf)[RH * LDS_PITCH], const float* __restrict__ power,
+                                                 int rows, int cols, int steps, int R0, int C0, int gr0, int gc0,
+                                                 float cc, float gx, float gy, float gz, float t_amb)
+{
+#if HS_UNROLL_T
+#pragma unroll 1
+#else
+#pragma unroll
+#endif
+    for (int s = 0; s < HS_TT; ++s) {
+        if (s >= steps)
+            break;
+        float* cur = buf[s & 1];
+#pragma unroll
+        for (int a = 0; a < HS_TY; ++a)
+#pragma unroll
+            for (int b = 0; b < HS_TX; ++b)
+                cur[(R0 + a) * LDS_PITCH + C0 + b] = v[a][b];
+        __syncthreads();
+
+        float nv[HS_TY][HS_TX];
+#pragma unroll
+        for (int a = 0; a < HS_TY; ++a) {
+            const int R = R0 + a, gr = gr0 + a;
+#pragma unroll
+            for (int b = 0; b < HS_TX; ++b) {
+                const int C = C0 + b, gc = gc0 + b;
+                const float t = v[a][b];
+                // Neighbours: the cell itself at the grid's edge; a register
+                // inside the thread's block; else LDS (the region's own edge
+                // reads the cell itself: such cells are never exact anyway).
+                float north, south, west, east;
+                if (EDGE && gr == 0) north = t;
+                else if (a > 0) north = v[a - 1][b];
+                else north = R > 0 ? cur[(R - 1) * LDS_PITCH + C] : t;
+                if (EDGE && gr == rows - 1) south = t;
+                else if (a < HS_TY - 1) south = v[a + 1][b];
+                else south = R < RH - 1 ? cur[(R + 1) * LDS_PITCH + C] : t;
+                if (EDGE && gc == 0) west = t;
+                else if (b > 0) west = v[a][b - 1];
+                else west = C > 0 ? cur[R * LDS_PITCH + C - 1] : t;
+                if (EDGE && gc == cols - 1) east = t;
+                else if (b < HS_TX - 1) east = v[a][b + 1];
+                else east = C < RW - 1 ? cur[R * LDS_PITCH + C + 1] : t;
+#if HS_SH_POWER
+                const float p = pw[a][b];
+#else
+                const float p = power[(size_t)clampi(gr, 0, rows - 1) * (size_t)cols + clampi(gc, 0, cols - 1)];
+#endif
+                nv[a][b] = cell_step(t, north, south, west, east, p, cc, gx, gy, gz, t_amb);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < HS_TY; ++a)
+#pragma unroll
+            for (int b = 0; b < HS_TX; ++b)
+                v[a][b] = nv[a][b];
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(HS_NT)
+HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* __restrict__ tout, int rows,
+        int cols, int steps, int tiles_x, int n_tiles, float cc, float gx, float gy, float gz, float t_amb)
+{
+    __shared__ float buf[2][RH * LDS_PITCH];
+    const int tile = xcd_remap((int)blockIdx.x, n_tiles);
+    const int tile_y = tile / tiles_x;
+    const int tile_x = tile - tile_y * tiles_x;
+    const int lx = (int)threadIdx.x % HS_BX;
+    const int ly = (int)threadIdx.x / HS_BX;
+    const int R0 = ly * HS_TY, C0 = lx * HS_TX;           // first cell of this thread in the region
+    const int rr0 = tile_y * OH - HS_TT, rc0 = tile_x * OW - HS_TT;   // the region's first global cell
+    const int gr0 = rr0 + R0, gc0 = rc0 + C0;              // the thread's first global cell
+
+    // The thread's cells (clamped reads outside the grid: those cells are
+    // never stored and never feed a cell inside the grid).
+    float v[HS_TY][HS_TX];
+    float pw[HS_TY][HS_TX];
+#pragma unroll
+    for (int a = 0; a < HS_TY; ++a) {
+        const size_t row = (size_t)clampi(gr0 + a, 0, rows - 1) * (size_t)cols;
+#pragma unroll
+        for (int b = 0; b < HS_TX; ++b) {
+            const int c = clampi(gc0 + b, 0, cols - 1);
+            v[a][b] = tin[row + c];
+            pw[a][b] = HS_SH_POWER ? power[row + c] : 0.0f;
+        }
+    }
+
+    // Workgroup-uniform: does the region touch (or cross) the grid's edge?
+    const bool edge = rr0 <= 0 || rc0 <= 0 || rr0 + RH >= rows || rc0 + RW >= cols;
+    if (edge)
+        run_steps<true>(v, pw, buf, power, rows, cols, steps, R0, C0, gr0, gc0, cc, gx, gy, gz, t_amb);
+    else
+        run_steps<false>(v, pw, buf, power, rows, cols, steps, R0, C0, gr0, gc0, cc, gx, gy, gz, t_amb);
+
+    // Store the inner tile.
+#pragma unroll
+    for (int a = 0; a < HS_TY; ++a) {
+        const int R = R0 + a, gr = gr0 + a;
+        if (R < HS_TT || R >= RH - HS_TT || gr >= rows)
+            continue;
+#pragma unroll
+        for (int b = 0; b < HS_TX; ++b) {
+            const int C = C0 + b, gc = gc0 + b;
+            if (C >= HS_TT && C < RW - HS_TT && gc < cols)
+                tout[(size_t)gr * (size_t)cols + gc] = v[a][b];
+        }
+    }
+}

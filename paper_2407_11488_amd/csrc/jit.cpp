@@ -70,15 +70,16 @@ static std::string hiprtc_version_str()
     return std::to_string(maj) + "." + std::to_string(min);
 }
 
-int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int vout,
-                   const std::string& arch, std::vector<char>* code, std::string* path, bool batch)
+int compile_program(const std::string& source, const char* name, const std::vector<std::string>& opts,
+                    const std::string& what, std::vector<char>* code, std::string* path)
 {
-    const std::vector<std::string> opts = direct_options(s, c, vin, vout, arch, batch);
-    uint64_t h = direct_source_hash();
+    uint64_t h = fnv1a(source);
     h = fnv1a(hiprtc_version_str(), h);
     for (const auto& o : opts) h = fnv1a(o + "\x1f", h);
     const std::string dir = code_cache_dir();
-    const std::string file = dir + "/direct_" + hex64(h) + ".co";
+    std::string stem(name);
+    stem = stem.substr(0, stem.find('.'));
+    const std::string file = dir + "/" + stem + "_" + hex64(h) + ".co";
     if (path) *path = file;
     std::vector<char> cached;
     if (read_file(file, cached) && cached.size() > 64) {
@@ -87,7 +88,7 @@ int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int v
     }
 
     hiprtcProgram prog = nullptr;
-    if (hiprtcCreateProgram(&prog, kDirectSource, "conv2d_direct.hip", 0, nullptr, nullptr) !=
+    if (hiprtcCreateProgram(&prog, source.c_str(), name, 0, nullptr, nullptr) !=
         HIPRTC_SUCCESS)
         return fail(CONV2D_ECOMPILE, "hiprtcCreateProgram failed");
     std::vector<const char*> argv;
@@ -99,7 +100,7 @@ int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int v
         std::string log(n + 1, '\0');
         if (n) hiprtcGetProgramLog(prog, &log[0]);
         hiprtcDestroyProgram(&prog);
-        return fail(CONV2D_ECOMPILE, "config " + config_str(c) + ": " + log.c_str());
+        return fail(CONV2D_ECOMPILE, what + ": " + log.c_str());
     }
     size_t n = 0;
     hiprtcGetCodeSize(prog, &n);
@@ -109,6 +110,52 @@ int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int v
     if (make_dirs(dir)) write_file_atomic(file, obj.data(), obj.size());  // best effort
     if (code) code->swap(obj);
     return CONV2D_OK;
+}
+
+int compile_source(const std::vector<std::string>& opts, const std::string& what, std::vector<char>* code,
+                   std::string* path)
+{
+    return compile_program(direct_source(), "conv2d_direct.hip", opts, what, code, path);
+}
+
+int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int vout,
+                   const std::string& arch, std::vector<char>* code, std::string* path, bool batch)
+{
+    return compile_source(direct_options(s, c, vin, vout, arch, batch), "config " + config_str(c), code, path);
+}
+
+std::string multi_kernel_name(const std::vector<MultiGroup>& groups)
+{
+    std::string n = "conv2d_multi";
+    for (const auto& g : groups) {
+        char b[96];
+        std::snprintf(b, sizeof b, "_f%dx%d_b%dx%d_t%dx%d_l%du%d", g.fh, g.fw, g.cfg.block_x, g.cfg.block_y,
+                      g.cfg.tile_x, g.cfg.tile_y, g.cfg.use_lds, g.cfg.unroll);
+        n += b;
+    }
+    return n;
+}
+
+std::vector<std::string> multi_options(int nt, const std::vector<MultiGroup>& groups, const std::string& arch)
+{
+    std::string list;
+    for (size_t k = 0; k < groups.size(); ++k) {
+        const MultiGroup& g = groups[k];
+        char b[128];
+        std::snprintf(b, sizeof b, "G(%zu,%d,%d,%d,%d,%d,%d,%d,%d)", k, g.fh, g.fw, g.cfg.block_x, g.cfg.block_y,
+                      g.cfg.tile_x, g.cfg.tile_y, g.cfg.use_lds, g.cfg.unroll);
+        list += b;
+    }
+    return {
+        "--offload-arch=" + arch,
+        "-O3",
+        "-std=c++17",
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-DCONV_BATCH=2",
+        "-DCONV_NT=" + std::to_string(nt),
+        "-DCONV_GROUPS=" + list,
+        "-DCONV_NAME=" + multi_kernel_name(groups),
+    };
 }
 
 int load_module(const std::vector<char>& code, const std::string& kernel, Module* m)

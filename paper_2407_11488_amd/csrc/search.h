@@ -1,0 +1,114 @@
+// The tuner's search machinery, independent of the kernel being tuned: a
+// measurer interface (compile a set of configurations, then verify and time
+// one), the exhaustive sweep over a candidate list, and the final re-timing
+// and tie-broken choice of the winner (Section 3 of the paper: compile and
+// benchmark every point of a restricted space; Section 4: tuning impact).
+// The convolution tuner and the hotspot tuner both run on it.
+#pragma once
+
+#include <algorithm>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace conv2d {
+
+enum MeasureStatus { kOk = 0, kCompile = CONV2D_ECOMPILE, kLaunch = CONV2D_ELAUNCH, kVerify = CONV2D_EVERIFY };
+const char* status_name(int s);
+int status_from(const std::string& n);
+// numpy's median (mean of the two middle values for an even count)
+double median_of(std::vector<double> v);
+// nearest-rank quantile, p in [0, 1]
+double quantile_nearest(std::vector<double> v, double p);
+
+template <class Cfg>
+struct RecordT {
+    Cfg c{};
+    int status = kOk;
+    double ms = 0, ms_min = 0, ms_p90 = 0;   // median, minimum, p90 of the timed launches
+    int reps = 0;
+};
+
+template <class Cfg>
+class MeasurerT {
+public:
+    virtual ~MeasurerT() = default;
+    virtual std::string arch() const = 0;
+    // Compile (or otherwise prepare) every config; status[i] gets kOk or a failure.
+    virtual int prepare(const std::vector<Cfg>& cfgs, std::vector<int>* status, double* seconds) = 0;
+    // Verify and time one prepared config (reps timed launches); best_so_far
+    // (0: none) lets a far slower point stop early.
+    virtual int measure(const Cfg& c, int warmup, int reps, double best_so_far, RecordT<Cfg>* r) = 0;
+};
+
+// Prepares and measures every configuration of `todo`, storing each record in
+// `done` under key(c) and passing it to sink(record). *best follows the
+// fastest verified time (0 = none yet); *compile_s accumulates compile time.
+template <class Cfg, class Key, class Sink>
+int measure_all(const std::vector<Cfg>& todo, MeasurerT<Cfg>* m, int warmup, int reps, bool verbose, Key key,
+                Sink sink, std::map<std::string, RecordT<Cfg>>* done, double* best, double* compile_s)
+{
+    std::vector<int> status;
+    double sec = 0;
+    int rc = m->prepare(todo, &status, &sec);
+    if (rc) return rc;
+    if (compile_s) *compile_s += sec;
+    for (size_t i = 0; i < todo.size(); ++i) {
+        RecordT<Cfg> r;
+        r.c = todo[i];
+        if (status[i] != kOk) {
+            r.status = status[i];
+        } else {
+            rc = m->measure(todo[i], warmup, reps, *best, &r);
+            if (rc) return rc;
+            if (r.status == kOk && (*best == 0 || r.ms < *best)) *best = r.ms;
+        }
+        (*done)[key(r.c)] = r;
+        sink(r);
+        if (verbose && ((i + 1) % 100 == 0 || i + 1 == todo.size()))
+            std::fprintf(stderr, "[tune] measured %zu/%zu, best %.4f ms\n", i + 1, todo.size(), *best);
+    }
+    return CONV2D_OK;
+}
+
+// Sorts `eligible` (verified records) by time, ties by less(); re-times the
+// n_top fastest with retime_reps repetitions (0: no re-timing) and sorts
+// again; the winner is the smallest configuration under less() whose time is
+// within tie_rel of the fastest.
+template <class Cfg, class Less>
+int retime_and_pick(std::vector<RecordT<Cfg>>* eligible, MeasurerT<Cfg>* m, int warmup, int retime_reps,
+                    int n_top, double tie_rel, Less less, RecordT<Cfg>* win)
+{
+    if (eligible->empty()) return fail(CONV2D_EVERIFY, "no configuration compiled, ran and verified");
+    auto by_time = [&](const RecordT<Cfg>& a, const RecordT<Cfg>& b) {
+        return a.ms != b.ms ? a.ms < b.ms : less(a.c, b.c);
+    };
+    std::sort(eligible->begin(), eligible->end(), by_time);
+    n_top = std::min<int>(n_top, (int)eligible->size());
+    if (retime_reps > 0 && n_top > 0) {
+        std::vector<Cfg> top;
+        for (int k = 0; k < n_top; ++k) top.push_back((*eligible)[k].c);
+        std::vector<int> st;
+        double sec = 0;
+        int rc = m->prepare(top, &st, &sec);
+        if (rc) return rc;
+        for (int k = 0; k < n_top; ++k) {
+            if (st[k] != kOk) continue;
+            RecordT<Cfg> r;
+            rc = m->measure(top[k], warmup, retime_reps, 0, &r);
+            if (rc) return rc;
+            if (r.status == kOk) (*eligible)[k] = r;
+        }
+        std::sort(eligible->begin(), eligible->end(), by_time);
+    }
+    const double fastest = (*eligible)[0].ms;
+    *win = (*eligible)[0];
+    for (const auto& r : *eligible)
+        if (r.ms <= fastest * (1.0 + tie_rel) && less(r.c, win->c)) *win = r;
+    return CONV2D_OK;
+}
+
+}  // namespace conv2d

@@ -14,6 +14,7 @@
 #include <thread>
 
 #include "internal.h"
+#include "search.h"
 
 namespace conv2d {
 
@@ -120,14 +121,9 @@ namespace {
 
 // ---------------------------------------------------------------- records
 
-enum Status { kOk = 0, kCompile = CONV2D_ECOMPILE, kLaunch = CONV2D_ELAUNCH, kVerify = CONV2D_EVERIFY };
+using Record = RecordT<conv2d_config>;
 
-struct Record {
-    conv2d_config c{};
-    int status = kOk;
-    double ms = 0, ms_min = 0, ms_p90 = 0;
-    int reps = 0;
-};
+}  // namespace
 
 const char* status_name(int s)
 {
@@ -164,6 +160,8 @@ double quantile_nearest(std::vector<double> v, double p)
     return v[std::min(rank, v.size()) - 1];
 }
 
+namespace {
+
 double gflops_of(const conv2d_shape& s, double ms)
 {
     return 2.0 * s.out_h * (double)s.out_w * s.filt_h * s.filt_w / (ms * 1e-3) / 1e9;
@@ -171,16 +169,9 @@ double gflops_of(const conv2d_shape& s, double ms)
 
 // ---------------------------------------------------------------- measurers
 
-class Measurer {
+class Measurer : public MeasurerT<conv2d_config> {
 public:
-    virtual ~Measurer() = default;
-    virtual std::string arch() const = 0;
     virtual int lds_limit() const = 0;
-    // Compile (or otherwise prepare) every config; status[i] gets kOk or a failure.
-    virtual int prepare(const std::vector<conv2d_config>& cfgs, std::vector<int>* status,
-                        double* seconds) = 0;
-    // Verify and time one prepared config (reps timed launches).
-    virtual int measure(const conv2d_config& c, int warmup, int reps, double best_so_far, Record* r) = 0;
 };
 
 class SyntheticMeasurer : public Measurer {
@@ -575,31 +566,16 @@ int tune_core(const conv2d_shape& s, const conv2d_tune_opts& o, Measurer* meas, 
         if (!done.count(config_str(c))) todo.push_back(c);
     res->n_resumed = (int)(candidates.size() - todo.size());
 
-    std::vector<int> status;
-    double compile_s = 0;
-    int rc = meas->prepare(todo, &status, &compile_s);
-    if (rc) return rc;
-    res->compile_s = compile_s;
-
     const double t0 = now_s();
     double best = 0;
     for (const auto& kv : done)
         if (kv.second.status == kOk && (best == 0 || kv.second.ms < best)) best = kv.second.ms;
-    for (size_t i = 0; i < todo.size(); ++i) {
-        Record r;
-        r.c = todo[i];
-        if (status[i] != kOk) {
-            r.status = status[i];
-        } else {
-            rc = meas->measure(todo[i], o.warmup, o.reps, best, &r);
-            if (rc) return rc;
-            if (r.status == kOk && (best == 0 || r.ms < best)) best = r.ms;
-        }
-        done[config_str(r.c)] = r;
+    auto key = [](const conv2d_config& c) { return config_str(c); };
+    auto sink = [&](const Record& r) {
         if (o.results_path && *o.results_path) append_line(o.results_path, result_line(meas->arch(), s, r));
-        if (o.verbose && ((i + 1) % 100 == 0 || i + 1 == todo.size()))
-            std::fprintf(stderr, "[tune] measured %zu/%zu, best %.4f ms\n", i + 1, todo.size(), best);
-    }
+    };
+    int rc = measure_all(todo, meas, o.warmup, o.reps, o.verbose != 0, key, sink, &done, &best, &res->compile_s);
+    if (rc) return rc;
 
     // Optional refinement: the ten fastest points again with every other
     // unroll value (the partial-unroll factor the paper makes tunable).
@@ -625,22 +601,8 @@ int tune_core(const conv2d_shape& s, const conv2d_tune_opts& o, Measurer* meas, 
         std::vector<conv2d_config> todo2;
         for (const auto& c : extra)
             if (!done.count(config_str(c))) todo2.push_back(c);
-        std::vector<int> st2;
-        double sec2 = 0;
-        rc = meas->prepare(todo2, &st2, &sec2);
+        rc = measure_all(todo2, meas, o.warmup, o.reps, false, key, sink, &done, &best, &res->compile_s);
         if (rc) return rc;
-        res->compile_s += sec2;
-        for (size_t i = 0; i < todo2.size(); ++i) {
-            Record r;
-            r.c = todo2[i];
-            if (st2[i] != kOk) r.status = st2[i];
-            else {
-                rc = meas->measure(todo2[i], o.warmup, o.reps, best, &r);
-                if (rc) return rc;
-            }
-            done[config_str(r.c)] = r;
-            if (o.results_path && *o.results_path) append_line(o.results_path, result_line(meas->arch(), s, r));
-        }
         for (const auto& c : extra) {
             legal.push_back(c);
             candidates.push_back(c);
@@ -665,37 +627,13 @@ int tune_core(const conv2d_shape& s, const conv2d_tune_opts& o, Measurer* meas, 
     res->n_timed = (int)eligible.size();
     if (eligible.empty()) return fail(CONV2D_EVERIFY, "no configuration compiled, ran and verified");
 
-    auto by_time = [](const Record& a, const Record& b) {
-        return a.ms != b.ms ? a.ms < b.ms : config_less(a.c, b.c);
-    };
-    std::sort(eligible.begin(), eligible.end(), by_time);
-
-    // Re-time the five fastest with more repetitions.
-    const int n_top = std::min<int>(5, (int)eligible.size());
-    if (o.retime_reps > 0) {
-        std::vector<conv2d_config> top;
-        for (int k = 0; k < n_top; ++k) top.push_back(eligible[k].c);
-        std::vector<int> st;
-        double sec = 0;
-        rc = meas->prepare(top, &st, &sec);
-        if (rc) return rc;
-        for (int k = 0; k < n_top; ++k) {
-            if (st[k] != kOk) continue;
-            Record r;
-            rc = meas->measure(top[k], o.warmup, o.retime_reps, 0, &r);
-            if (rc) return rc;
-            if (r.status == kOk) eligible[k] = r;
-        }
-        std::sort(eligible.begin(), eligible.end(), by_time);
-    }
-    res->measure_s = now_s() - t0;
+    // Re-time the five fastest with more repetitions; the winner is the
+    // lowest time, ties within tie_rel going to the smallest tuple.
+    Record win;
+    rc = retime_and_pick(&eligible, meas, o.warmup, o.retime_reps, 5, o.tie_rel, config_less, &win);
+    if (rc) return rc;
+    res->measure_s = now_s() - t0 - res->compile_s;
     res->evaluations = (int)(candidates.size()) - res->n_resumed;
-
-    // Winner: lowest time; ties within tie_rel go to the smallest tuple.
-    const double fastest = eligible[0].ms;
-    Record win = eligible[0];
-    for (const auto& r : eligible)
-        if (r.ms <= fastest * (1.0 + o.tie_rel) && config_less(r.c, win.c)) win = r;
     res->best = win.c;
     res->best_ms = win.ms;
     for (int k = 0; k < 5; ++k) {

@@ -10,6 +10,9 @@ winner applied unchanged):
     python -m paper_2407_11488_amd.tune --size 4096 --filters 3 7 15 31 --ref-filter 17 \
         --results-dir DIR
 
+Hotspot stencil (the second tunable kernel), one grid and step count:
+    python -m paper_2407_11488_amd.tune --hotspot 4096 4096 --steps 60 [--results PATH]
+
 Prints JSON reports: the winner and its throughput, the top five, the median,
 the tuning impact (best over median throughput, the paper's Section 4
 metric), tuned/default, and compile/launch/verify failure counts. Winners are
@@ -72,6 +75,31 @@ def tune_one(shape, a, results_path):
     return rep
 
 
+HOTSPOT_WINNERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "hotspot_winners.jsonl")
+
+
+def tune_hotspot(rows, cols, steps, a, results_path):
+    o = B.hotspot_tune_defaults()
+    o.winners_path = HOTSPOT_WINNERS.encode() if a.winners == DEFAULT_WINNERS else a.winners.encode()
+    o.results_path = results_path.encode() if results_path else None
+    o.reps, o.retime_reps, o.warmup = a.reps, a.retime_reps, a.warmup
+    o.flush_mall = 0 if a.no_flush else 1
+    o.max_configs, o.threads, o.verbose = a.max_configs, a.threads, 1
+    r = B.hotspot_tune(B.hotspot_shape(rows, cols), steps, o)
+    top = [{"config": list(r.top[k].tuple()), "ms": round(r.top_ms[k], 5)} for k in range(5) if r.top_ms[k] > 0]
+    return {
+        "workload": "hotspot", "grid": [rows, cols], "steps": steps,
+        "winner": list(r.best.tuple()), "best_ms": round(r.best_ms, 5), "best_gflops": round(r.best_gflops, 1),
+        "median_gflops": round(r.median_gflops, 1), "impact": round(r.impact, 3),
+        "default_ms": round(r.default_ms, 5), "default_gflops": round(r.default_gflops, 1),
+        "tuned_vs_default": round(r.default_ms / r.best_ms, 3) if r.default_ms > 0 else None,
+        "default_rank": r.default_rank, "n_space": r.n_space, "n_illegal": r.n_illegal, "n_timed": r.n_timed,
+        "n_compile_fail": r.n_compile_fail, "n_launch_fail": r.n_launch_fail, "n_verify_fail": r.n_verify_fail,
+        "n_resumed": r.n_resumed, "compile_s": round(r.compile_s, 1), "measure_s": round(r.measure_s, 1),
+        "top5": top,
+    }
+
+
 def emit(rep, path):
     line = json.dumps(rep)
     print(line, flush=True)
@@ -102,7 +130,16 @@ def main(argv=None) -> int:
     ap.add_argument("--max-evals", type=int, default=100)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--hotspot", type=int, nargs=2, metavar=("ROWS", "COLS"))
+    ap.add_argument("--steps", type=int, default=60)
     a = ap.parse_args(argv)
+
+    if a.hotspot:
+        rows, cols = a.hotspot
+        results = a.results or os.path.join(os.path.dirname(DEFAULT_WINNERS),
+                                            f"hotspot_results_gfx950_{rows}x{cols}_s{a.steps}.jsonl")
+        emit(tune_hotspot(rows, cols, a.steps, a, results), a.json)
+        return 0
 
     if a.shape:
         emit(tune_one(tuple(a.shape), a, a.results), a.json)

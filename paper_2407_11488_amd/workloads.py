@@ -83,12 +83,16 @@ def batch_benchmark(reps: int = 20, warmup: int = 3, n: int = 64) -> dict:
 
     b_ms, b_wall = timed(run_batch, reps)
     p_ms, p_wall = timed(run_plain, reps)
+    per_group = Batch(shapes, flags=B.CONV2D_BATCH_PER_GROUP)
+    g_ms, _ = timed(lambda: per_group(ins, fs, outs), reps)
+    per_group.close()
     res = {
         "workload": f"{n} convolutions, sides log-uniform [256, 2048], filters {{3,5,9,17}}",
         "gflop": round(flops / 1e9, 3),
         "batch_ms": round(b_ms, 4), "batch_gflops": round(flops / (b_ms * 1e-3) / 1e9, 1),
         "plain_ms": round(p_ms, 4), "plain_gflops": round(flops / (p_ms * 1e-3) / 1e9, 1),
         "speedup": round(p_ms / b_ms, 3),
+        "per_group_kernels_ms": round(g_ms, 4),
         "batch_wall_ms": round(b_wall, 4), "plain_wall_ms": round(p_wall, 4),
         "groups": batch.info["groups"], "total_tiles": batch.info["total_tiles"],
     }
@@ -134,11 +138,12 @@ def serve_benchmark(duration: float = 60.0, rates=(0.8,), budget_gib: float = 8.
     for frac in rates:
         rate = frac * cap_serial
         reqs = _trace(rate, duration)
-        run = {"rate_fraction_of_serial_capacity": frac, "rate_req_s": round(rate, 1), "n": len(reqs),
-               "batched": _serve(reqs, False, budget, streams, max_batch),
-               "serial": _serve(reqs, True, budget, streams, max_batch)}
+        run = {"rate_fraction_of_serial_capacity": frac, "rate_req_s": round(rate, 1), "n": len(reqs)}
+        for mode, serial in (("batched", False), ("serial", True)):
+            run[mode] = _serve(reqs, serial, budget, streams, max_batch)
+            print(f"[serve] rate {frac} x serial capacity, {mode}: p50 {run[mode]['p50_ms']} ms, "
+                  f"p99 {run[mode]['p99_ms']} ms", file=sys.stderr, flush=True)
         out["runs"].append(run)
-        print(f"[serve] rate {frac} x serial capacity done", file=sys.stderr, flush=True)
     return out
 
 

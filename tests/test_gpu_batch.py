@@ -33,13 +33,15 @@ def workload():
     return shapes, list(ins), list(fs)
 
 
-def test_batch_uneven_workload_matches_oracle_and_plain(workload):
+@pytest.mark.parametrize("flags", [0, C.CONV2D_BATCH_PER_GROUP])
+def test_batch_uneven_workload_matches_oracle_and_plain(workload, flags):
     """64 problems, square outputs log-uniform in [256, 2048], filters from
     {3, 5, 9, 17}: every output within tolerance of the FP64 oracle and bitwise
-    equal to a plain conv2d_run of the same problem."""
+    equal to a plain conv2d_run of the same problem (multi-filter kernel, and
+    one kernel per filter size)."""
     torch = torch_cuda()
     shapes, ins, fs = workload
-    batch = C.Batch(shapes)
+    batch = C.Batch(shapes, flags=flags)
     say(f"batch groups {batch.info}")
     outs = [torch.full((H, W), float("nan"), device="cuda") for (H, W, _, _) in shapes]
     batch(ins, fs, outs)
@@ -109,6 +111,29 @@ def test_batch_edge_cases():
             ref, s = oracle.conv2d_f64(inp, f)
             assert oracle.normalized_error(outs[p].cpu().numpy(), ref, s) <= TOL
         b.close()
+
+
+def test_batch_many_filter_sizes():
+    """Eleven filter sizes (more than one multi-filter kernel holds), uneven
+    images, integer data: bitwise equal to the oracle on every replay."""
+    torch = torch_cuda()
+    filters = [(1, 1), (3, 3), (5, 5), (7, 7), (9, 9), (11, 11), (2, 6), (6, 2), (17, 17), (31, 31), (4, 4)]
+    shapes = [(40 + 13 * k, 70 - 5 * k, fh, fw) for k, (fh, fw) in enumerate(filters)]
+    shapes += [(9, 300, fh, fw) for fh, fw in filters[::3]]
+    probs = [datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=700 + p, seed_f=800 + p)
+             for p, (H, W, fh, fw) in enumerate(shapes)]
+    ins = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a, _ in probs]
+    fs = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for _, f in probs]
+    b = C.Batch(shapes)
+    say(f"many filters: {b.info['n_groups']} groups")
+    assert b.info["n_groups"] == len(filters)
+    for rep in range(3):
+        outs = b(ins, fs)
+        torch.cuda.synchronize()
+        for p, (inp, f) in enumerate(probs):
+            ref, _ = oracle.conv2d_f64(inp, f)
+            assert np.array_equal(outs[p].cpu().numpy().astype(np.float64), ref), (rep, p)
+    b.close()
 
 
 def test_batch_errors():

@@ -1,0 +1,153 @@
+"""GPU parity of the hotspot stencil (hotspot_plan / hotspot_run /
+hotspot_reference) through the C ABI: the one-step reference against the FP64
+oracle, a stratified sample of the tuning space bitwise against the reference,
+the 4096 x 4096 chip workload against the oracle, edge cases and errors."""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests.gpu_util import say, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+C = pytest.importorskip("paper_2407_11488_amd")
+
+STRESS = (0.2, 0.5, 0.75, 0.05, 0.25)   # every term of the step matters at this scale
+
+
+def bound(temp, power, steps, k):
+    """FP32 error bound of `steps` explicit steps (each step's rounding is at
+    most a few units in the last place of the largest term it touches, and a
+    stable step does not amplify earlier errors): 8 n u (max|T| + |t_amb| +
+    n cc max|P|)."""
+    cc, _, _, _, t_amb = k
+    m = float(np.max(np.abs(temp))) + abs(t_amb) + steps * cc * float(np.max(np.abs(power)))
+    return 8.0 * max(steps, 1) * 2.0 ** -24 * m
+
+
+def _run_plan(cfg, temp_d, power_d, steps, k, rows, cols):
+    torch = torch_cuda()
+    plan = C.Hotspot(rows, cols, cfg)
+    try:
+        out = torch.full((rows, cols), float("nan"), device="cuda")
+        plan(temp_d, power_d, steps, k, out=out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("rows,cols,steps", [(1, 1, 3), (1, 17, 4), (33, 1, 5), (64, 64, 1), (100, 77, 13),
+                                             (5, 300, 0)])
+def test_reference_matches_oracle(rows, cols, steps):
+    torch = torch_cuda()
+    temp = datagen.uniform_pm1(61, rows * cols).reshape(rows, cols)
+    power = datagen.uniform_pm1(62, rows * cols).reshape(rows, cols)
+    out = C.hotspot_reference(to_dev(temp), to_dev(power), steps, STRESS)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = oracle.hotspot_f64(temp, power, steps, *STRESS)
+    assert np.max(np.abs(got - ref)) <= bound(temp, power, steps, STRESS)
+
+
+def test_stratified_configs_bitwise():
+    """About 130 points of the space (every 16th in enumeration order, plus the
+    default and the extremes of each axis) on a ragged 181 x 97 grid, 13 steps
+    (partial last launches for most temporal factors): every point equals the
+    reference bit for bit."""
+    torch = torch_cuda()
+    rows, cols, steps = 181, 97, 13
+    space = C.hotspot_space(C.hotspot_shape(rows, cols))
+    pick = space[::16] + [C.hotspot_default_config().tuple()]
+    for ax in range(7):
+        vals = sorted({c[ax] for c in space})
+        for v in (vals[0], vals[-1]):
+            pick.append(next(c for c in space if c[ax] == v))
+    pick = sorted(set(pick))
+    with cf.ThreadPoolExecutor(16) as ex:
+        list(ex.map(C.hotspot_compile, pick))
+    temp = datagen.uniform_pm1(63, rows * cols).reshape(rows, cols)
+    power = datagen.uniform_pm1(64, rows * cols).reshape(rows, cols)
+    td, pd = to_dev(temp), to_dev(power)
+    ref = C.hotspot_reference(td, pd, steps, STRESS)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    assert np.max(np.abs(ref - oracle.hotspot_f64(temp, power, steps, *STRESS))) <= bound(temp, power, steps, STRESS)
+    say(f"hotspot: {len(pick)} configurations")
+    for cfg in pick:
+        got = _run_plan(cfg, td, pd, steps, STRESS, rows, cols)
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), cfg
+
+
+def test_chip_workload_full_size():
+    """4096 x 4096 chip workload, 60 steps, in the configuration the plan picks
+    (the tuned winner when cached): every cell within the bound of the FP64
+    oracle."""
+    torch = torch_cuda()
+    rows = cols = 4096
+    steps = 60
+    temp, power, k = datagen.hotspot_problem(rows, cols)
+    plan = C.Hotspot(rows, cols)
+    say(f"hotspot 4096 with {plan.source} config {plan.config}")
+    out = plan(to_dev(temp), to_dev(power), steps, k)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    plan.close()
+    ref = oracle.hotspot_f64(temp, power, steps, *k)
+    err = float(np.max(np.abs(got - ref)))
+    say(f"hotspot 4096 max error {err:.3e} K (bound {bound(temp, power, steps, k):.3e})")
+    assert err <= bound(temp, power, steps, k)
+
+
+def test_edge_cases():
+    """Zero steps copy the grid; a grid smaller than one output tile; the same
+    plan reused on new data; a temporal factor above the step count."""
+    torch = torch_cuda()
+    for rows, cols, steps, cfg in [(7, 5, 0, None), (3, 2, 9, (16, 4, 4, 4, 6, 0, 1)), (2, 1, 2, (64, 2, 1, 4, 3, 1, 0))]:
+        temp = datagen.uniform_pm1(65, rows * cols).reshape(rows, cols)
+        power = datagen.uniform_pm1(66, rows * cols).reshape(rows, cols)
+        got = _run_plan(cfg, to_dev(temp), to_dev(power), steps, STRESS, rows, cols)
+        ref = oracle.hotspot_f64(temp, power, steps, *STRESS)
+        assert np.max(np.abs(got - ref)) <= bound(temp, power, steps, STRESS), (rows, cols, steps, cfg)
+    plan = C.Hotspot(40, 40, (32, 8, 2, 1, 2, 1, 1))
+    for seed in (67, 68):
+        temp = datagen.uniform_pm1(seed, 1600).reshape(40, 40)
+        got = plan(to_dev(temp), to_dev(temp * 0), 5, STRESS)
+        torch.cuda.synchronize()
+        ref = oracle.hotspot_f64(temp, temp * 0, 5, *STRESS)
+        assert np.max(np.abs(got.cpu().numpy() - ref)) <= bound(temp, temp * 0, 5, STRESS)
+    plan.close()
+
+
+def test_errors_are_reported_not_faulted():
+    torch = torch_cuda()
+    s = C.hotspot_shape(64, 64)
+    h = C.hotspot_plan(s, (32, 8, 1, 1, 2, 1, 1))
+    k = C.hotspot_coeffs(*STRESS)
+    st = torch.cuda.current_stream().cuda_stream
+    try:
+        a = torch.zeros((64, 64), device="cuda")
+        b = torch.zeros((64, 64), device="cuda")
+        o = torch.zeros((64, 64), device="cuda")
+        small = torch.zeros((10, 10), device="cuda")
+        with pytest.raises(C.Conv2dError):        # two launches, no work buffer
+            C.hotspot_run(h, a.data_ptr(), b.data_ptr(), o.data_ptr(), 0, 3, k, st)
+        with pytest.raises(C.Conv2dError):        # output overlaps the input
+            C.hotspot_run(h, a.data_ptr(), b.data_ptr(), a.data_ptr(), 0, 1, k, st)
+        with pytest.raises(C.Conv2dError):        # buffer too small for the grid
+            C.hotspot_run(h, small.data_ptr(), b.data_ptr(), o.data_ptr(), 0, 1, k, st)
+        with pytest.raises(C.Conv2dError):
+            C.hotspot_run(h, a.data_ptr(), b.data_ptr(), o.data_ptr(), 0, -1, k, st)
+        with pytest.raises(C.Conv2dError):        # work buffer is the output
+            C.hotspot_run(h, a.data_ptr(), b.data_ptr(), o.data_ptr(), o.data_ptr(), 3, k, st)
+        C.hotspot_run(h, a.data_ptr(), b.data_ptr(), o.data_ptr(), 0, 2, k, st)   # one launch: no work buffer
+        torch.cuda.synchronize()
+    finally:
+        C.hotspot_destroy(h)
+    with pytest.raises(C.Conv2dError):
+        C.hotspot_plan(s, (16, 1, 1, 1, 1, 1, 1))    # 16 threads: below the minimum
+    with pytest.raises(C.Conv2dError):
+        C.hotspot_plan(C.hotspot_shape(0, 5))

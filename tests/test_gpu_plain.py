@@ -137,18 +137,20 @@ def test_unroll_and_alignment_variants(cfg):
     assert np.array_equal(got.cpu().numpy().view(np.uint32), out.cpu().numpy().view(np.uint32))
 
 
-def test_full_size_sampled():
-    """4096x4096 / 17x17 (the tuned workload) with the configuration the plan
-    picks: sampled outputs (corners, edges, random interior) against the oracle
+@pytest.mark.parametrize("fsize", [17, 3, 5, 7, 9, 15, 31])
+def test_full_size_sampled(fsize):
+    """4096x4096 outputs with each filter of the filter-size sweep, in the
+    configuration the plan picks (the tuned winner when the winners cache holds
+    one): sampled outputs (corners, edges, random interior) against the oracle
     computed point by point; every output finite."""
     torch = torch_cuda()
     H = W = 4096
-    fh = fw = 17
+    fh = fw = fsize
     n_in = (H + fh - 1) * (W + fw - 1)
     inp = datagen.uniform_pm1(1, n_in).reshape(H + fh - 1, W + fw - 1)
     f = datagen.uniform_pm1(2, fh * fw).reshape(fh, fw)
     plan = C.Plan(H, W, fh, fw)
-    say(f"full size 4096 f17 with {plan.source} config {plan.config}")
+    say(f"full size 4096 f{fsize} with {plan.source} config {plan.config}")
     out = plan(to_dev(inp), to_dev(f), out=nan_like(H, W))
     torch.cuda.synchronize()
     got = out.cpu().numpy()

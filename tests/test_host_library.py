@@ -238,3 +238,62 @@ def test_local_search_follows_its_definition(tmp_path, seed, budget):
     if budget >= len(legal):
         ok = {c: t for c, t in table.items() if c not in fails}
         assert best == min(ok, key=lambda c: (ok[c], c))
+
+
+# ---------------------------------------------------------------- hotspot
+
+HS_HEADER = os.path.join(ROOT, "include", "hotspot.h")
+
+
+def test_library_exports_every_hotspot_function():
+    text = re.sub(r"/\*.*?\*/", "", open(HS_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(hotspot_[a-z0-9_]+)\s*\(", text)))
+    assert len(names) >= 12
+    assert not [n for n in names if not hasattr(C.lib, n)]
+
+
+def test_hotspot_space_matches_oracle_enumeration():
+    got = C.hotspot_space(C.hotspot_shape(4096, 4096))
+    assert got == ospace.hotspot_restricted()
+    assert len(got) == 2040
+    assert all(C.hotspot_lds_bytes(c) <= 163840 for c in got)
+
+
+def test_hotspot_config_check_errors():
+    s = C.hotspot_shape(64, 64)
+    assert C.hotspot_config_check(s, (32, 8, 1, 1, 1, 1, 1)) == 0
+    for bad in [(16, 2, 1, 1, 1, 1, 1),      # 32 threads
+                (48, 2, 1, 1, 1, 1, 1),      # block_x off its axis
+                (256, 8, 1, 1, 1, 1, 1),     # 2048 threads
+                (64, 1, 1, 1, 1, 1, 1),      # one region row: not larger than 2 * temporal
+                (32, 4, 1, 2, 4, 1, 1),      # 8 rows, temporal 4
+                (32, 8, 3, 1, 1, 1, 1),      # tile_x off its axis
+                (32, 8, 1, 1, 5, 1, 1),      # temporal off its axis
+                (32, 8, 1, 1, 1, 2, 1),
+                (32, 8, 1, 1, 1, 1, 2)]:
+        assert C.hotspot_config_check(s, bad) == C.CONV2D_EINVAL, bad
+        assert C.conv2d_last_error()
+    # 16384 cells in two buffers need 131,200 bytes of LDS: legal at 160 KiB,
+    # rejected under a 64 KiB limit
+    assert C.hotspot_lds_bytes((256, 4, 4, 4, 1, 1, 1)) == 131200
+    assert C.hotspot_config_check(s, (256, 4, 4, 4, 1, 1, 1)) == 0
+    assert C.hotspot_config_check(s, (256, 4, 4, 4, 1, 1, 1), 65536) == C.CONV2D_EINVAL
+    assert C.hotspot_config_check(C.hotspot_shape(0, 4), (32, 8, 1, 1, 1, 1, 1)) == C.CONV2D_EINVAL
+
+
+@pytest.mark.parametrize("cfg", [(32, 8, 1, 1, 1, 1, 1), (64, 4, 2, 4, 4, 0, 1), (16, 16, 4, 4, 6, 0, 0),
+                                 (128, 2, 4, 2, 1, 1, 0), (128, 8, 1, 4, 8, 0, 1)])
+def test_hotspot_code_is_plain_fp32_without_spills(cfg):
+    """No packed FP32 instruction; six FMAs per cell and step (four written,
+    and (N + S) - 2T contracted twice, which is exact since 2T is) in each of
+    the two step loops (grid edge, interior), fully unrolled or one step
+    rolled; LDS within the stated bound; no scratch."""
+    path = C.hotspot_compile(cfg)
+    isa = subprocess.run([OBJDUMP, "-d", path], capture_output=True, text=True).stdout
+    assert "v_pk_" not in isa
+    bx, by, tx, ty, tt, unroll_t, _ = cfg
+    steps_in_code = 1 if unroll_t else tt
+    assert isa.count("v_fmac_f32") + isa.count("v_fma_f32") == 2 * 6 * tx * ty * steps_in_code
+    n = _notes(path)
+    assert n["private_segment_fixed_size"] == 0 and n["vgpr_spill_count"] == 0
+    assert 0 < n["group_segment_fixed_size"] <= C.hotspot_lds_bytes(cfg)

@@ -18,6 +18,7 @@ import oracle
 HERE = os.path.dirname(os.path.abspath(__file__))
 EMU = os.path.join(HERE, "emu")
 KERNEL = os.path.join(os.path.dirname(HERE), "paper_2407_11488_amd", "csrc", "conv2d_direct.hip")
+HOTSPOT = os.path.join(os.path.dirname(HERE), "paper_2407_11488_amd", "csrc", "hotspot.hip")
 CXX = "/opt/rocm/llvm/bin/clang++"
 BIN_DIR = os.path.join(tempfile.gettempdir(), "conv2d_emu_bins")
 
@@ -152,3 +153,104 @@ def test_emulated_batch_kernel_exact(fh, fw, tmp_path):
             for k, (H, W, ref) in enumerate(probs):
                 got = np.fromfile(tmp_path / f"out{k}.f32", np.float32).reshape(H, W)
                 assert np.array_equal(got.astype(np.float64), ref), (cfg, grid, k)
+
+
+# Groups of the multi-filter kernel (k, FH, FW, BX, BY, TX, TY, LDS, UNROLL),
+# 64 threads each, covering LDS and global-memory groups, x and y tiling,
+# non-square filters and the rolled and unrolled row loops.
+MULTI_GROUPS = [(0, 5, 5, 16, 4, 2, 2, 1, 1), (1, 3, 3, 64, 1, 4, 4, 0, 1), (2, 4, 2, 8, 8, 1, 3, 1, 2),
+                (3, 1, 1, 32, 2, 8, 1, 0, 0)]
+
+
+def build_multi(groups, nt):
+    glist = "".join("G(%s)" % ",".join(str(v) for v in g) for g in groups)
+    defs = {"CONV_BATCH": "2", "CONV_NT": str(nt), "CONV_GROUPS": glist, "CONV_NAME": "conv2d_multi"}
+    src = open(KERNEL).read() + open(os.path.join(EMU, "emu_multi.cpp")).read() + \
+        open(os.path.join(EMU, "hip_emu.h")).read()
+    key = hashlib.sha1((src + repr(sorted(defs.items()))).encode()).hexdigest()[:16]
+    os.makedirs(BIN_DIR, exist_ok=True)
+    exe = os.path.join(BIN_DIR, f"emum_{key}")
+    if not os.path.exists(exe):
+        cmd = [CXX, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+               "-fno-omit-frame-pointer", *[f"-D{k}={v}" for k, v in defs.items()],
+               os.path.join(EMU, "emu_multi.cpp"), "-o", exe + ".tmp", "-lpthread"]
+        subprocess.run(cmd, check=True, capture_output=True)
+        os.replace(exe + ".tmp", exe)
+    return exe
+
+
+def test_emulated_multi_filter_kernel_exact(tmp_path):
+    """The multi-filter persistent kernel over uneven images of four filter
+    sizes: every output of every image written once and exact, over two
+    launches, for several grid sizes; the tile counters return to 0."""
+    sizes = [(37, 45, 0), (5, 130, 1), (64, 64, 2), (1, 1, 3), (19, 7, 0), (33, 9, 2), (8, 200, 1), (3, 3, 3)]
+    probs = []
+    for k, (H, W, g) in enumerate(sizes):
+        fh, fw = MULTI_GROUPS[g][1], MULTI_GROUPS[g][2]
+        inp, f = datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=300 + k, seed_f=400 + k)
+        inp.astype(np.float32).tofile(tmp_path / f"in{k}.f32")
+        f.astype(np.float32).tofile(tmp_path / f"f{k}.f32")
+        probs.append((H, W, g, oracle.conv2d_f64(inp, f)[0]))
+    exe = build_multi(MULTI_GROUPS, 64)
+    args = [str(v) for H, W, g, _ in probs for v in (H, W, g)]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    for grid in (1, 7, 16):
+        r = subprocess.run([exe, str(grid), str(tmp_path), str(len(probs)), *args], capture_output=True,
+                           text=True, env=env, timeout=300)
+        assert r.returncode == 0, r.stderr[-3000:]
+        for k, (H, W, g, ref) in enumerate(probs):
+            got = np.fromfile(tmp_path / f"out{k}.f32", np.float32).reshape(H, W)
+            assert np.array_equal(got.astype(np.float64), ref), (grid, k)
+
+
+# Hotspot configurations (block_x, block_y, tile_x, tile_y, temporal,
+# unroll_t, sh_power): one cell per thread, x and y tiling, temporal factors
+# from 1 to 8 with full and partial last launches, both power modes.
+HOTSPOT_CONFIGS = [(16, 4, 1, 1, 1, 1, 1), (32, 2, 2, 4, 2, 0, 0), (16, 8, 4, 2, 3, 1, 1), (64, 1, 1, 4, 1, 0, 1),
+                   (16, 16, 1, 1, 6, 0, 0), (32, 4, 2, 4, 3, 1, 0), (16, 8, 4, 4, 8, 0, 1)]
+
+
+def build_hotspot(cfg):
+    bx, by, tx, ty, tt, u, p = cfg
+    defs = dict(BX=bx, BY=by, TX=tx, TY=ty, TT=tt, UNROLL_T=u, SH_POWER=p)
+    src = open(HOTSPOT).read() + open(os.path.join(EMU, "emu_hotspot.cpp")).read() + \
+        open(os.path.join(EMU, "hip_emu.h")).read()
+    key = hashlib.sha1((src + repr(sorted(defs.items()))).encode()).hexdigest()[:16]
+    os.makedirs(BIN_DIR, exist_ok=True)
+    exe = os.path.join(BIN_DIR, f"emuh_{key}")
+    if not os.path.exists(exe):
+        cmd = [CXX, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+               "-fno-omit-frame-pointer", *[f"-DHS_{k}={v}" for k, v in defs.items()],
+               "-DHS_NAME=hotspot_emu", os.path.join(EMU, "emu_hotspot.cpp"), "-o", exe + ".tmp", "-lpthread"]
+        subprocess.run(cmd, check=True, capture_output=True)
+        os.replace(exe + ".tmp", exe)
+    return exe
+
+
+def test_emulated_hotspot_kernel(tmp_path):
+    """The temporally tiled hotspot kernel on uneven grids (smaller than one
+    tile, several tiles with ragged edges, one row, one column): every
+    configuration returns the same bits, within the FP32 bound of the FP64
+    oracle."""
+    with cf.ThreadPoolExecutor(os.cpu_count() or 4) as ex:
+        exes = list(ex.map(build_hotspot, HOTSPOT_CONFIGS))
+    k = (0.2, 0.5, 0.75, 0.05, 0.25)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    for (rows, cols, steps) in [(37, 45, 7), (5, 130, 3), (1, 9, 4), (23, 1, 5), (70, 3, 9), (2, 2, 0)]:
+        temp = datagen.uniform_pm1(61, rows * cols).reshape(rows, cols)
+        power = datagen.uniform_pm1(62, rows * cols).reshape(rows, cols)
+        temp.tofile(tmp_path / "temp.f32")
+        power.tofile(tmp_path / "power.f32")
+        ref = oracle.hotspot_f64(temp, power, steps, *k)
+        bound = 8 * max(steps, 1) * 2.0 ** -24 * (1.0 + abs(k[4]) + steps * k[0] * 1.0)
+        first = None
+        for cfg, exe in zip(HOTSPOT_CONFIGS, exes):
+            r = subprocess.run([exe, str(rows), str(cols), str(steps), *[repr(v) for v in k], str(tmp_path)],
+                               capture_output=True, text=True, env=env, timeout=300)
+            assert r.returncode == 0, r.stderr[-3000:]
+            got = np.fromfile(tmp_path / "out.f32", np.float32).reshape(rows, cols)
+            assert np.all(np.isfinite(got)), (cfg, rows, cols)
+            assert np.max(np.abs(got - ref)) <= bound, (cfg, rows, cols, np.max(np.abs(got - ref)))
+            if first is None:
+                first = got
+            assert np.array_equal(got.view(np.uint32), first.view(np.uint32)), (cfg, rows, cols)
