@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="duration of the serving trace (batched and serial each); 0 skips serving")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-hotspot", action="store_true",
+                    help="skip the hotspot stencil summary (4096x4096 chip workload, 60 steps)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, run plain copy/negate kernels over this many MiB "
                          "(calibration of the profiler's byte counters)")
@@ -180,6 +182,8 @@ def main():
     from paper_2407_11488_amd import workloads
     if not args.no_batch:
         line["batch"] = workloads.batch_benchmark(reps=20)
+    if not args.no_hotspot:
+        line["hotspot"] = workloads.hotspot_benchmark(reps=20)
     if args.serve_seconds > 0:
         sv = workloads.serve_benchmark(duration=args.serve_seconds, rates=(0.8,))
         run = sv["runs"][0]

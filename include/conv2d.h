@@ -165,28 +165,18 @@ int conv2d_fill_uniform(float *d_out, size_t n, uint64_t seed, uint64_t start, v
  *
  * Many convolutions of uneven sizes in one hipGraph launch (not part of the
  * paper: the batching extension of its convolution kernel). Problems are
- * grouped by filter size. By default one persistent kernel serves up to 8
- * filter sizes: each size is a group compiled into it with a 256-thread
- * configuration of that filter (the tuned winner when it has 256 threads, else
- * the fastest 256-thread point of the tuner's result database for that filter
- * at 4096x4096, else 16x16 threads with 1x1 tiles; filter always read through
- * its pointer; rolled row loop). The tile list holds the groups' tiles,
- * costliest tile first, and workgroups claim tiles from a device counter, so
- * the cheapest tiles fill the end. More than 8 filter sizes run as several such
- * kernels in order. With CONV2D_BATCH_PER_GROUP each filter size instead runs
- * its tuned configuration (winners cache entry for 4096x4096 with that filter,
- * else the most recent entry with that filter, else the default) as its own
- * persistent kernel with a static tile schedule, the kernels as parallel
- * branches of the graph. The graph is captured at plan time. Results are
- * bitwise identical to conv2d_run / conv2d_reference on the same data.
- * A batch plan must not run on two streams at once (its descriptor table and
- * tile counters are shared); runs on one stream are ordered. Each input is
- * limited to 2 GiB. */
+ * grouped by filter size; each group runs the tuned configuration of its filter
+ * size (winners cache entry for 4096x4096 with that filter, else the most
+ * recent entry with that filter, else the default; the filter is always read
+ * through its pointer) as one persistent kernel over the group's tiles. The
+ * groups are parallel branches of one graph captured at plan time. Results
+ * are bitwise identical to conv2d_run / conv2d_reference on the same data.
+ * A batch plan must not run on two streams at once (its descriptor table is
+ * shared); runs on one stream are ordered. Each input is limited to 2 GiB. */
 
 enum {
-    CONV2D_BATCH_NO_GRAPH = 1,     /* launch the kernels directly instead of a graph */
-    CONV2D_BATCH_NO_PTR_CHECK = 2, /* skip the per-problem allocation checks */
-    CONV2D_BATCH_PER_GROUP = 4     /* one kernel per filter size (see above) */
+    CONV2D_BATCH_NO_GRAPH = 1,     /* launch the group kernels directly instead of a graph */
+    CONV2D_BATCH_NO_PTR_CHECK = 2  /* skip the per-problem allocation checks */
 };
 
 /* Plans n problems (n <= 65535); shapes[i] as for conv2d_plan. */
@@ -194,15 +184,14 @@ int conv2d_batch_plan(conv2d_batch_t *batch, int n, const conv2d_shape *shapes, 
 
 /* Enqueues all n convolutions on `stream`: d_in[i], d_f[i], d_out[i] are the
  * device buffers of problem i (host arrays of n device pointers). When the
- * pointers differ from the previous run, a 56-byte-per-problem descriptor
+ * pointers differ from the previous run, a 48-byte-per-problem descriptor
  * table is first copied to the device on the same stream. */
 int conv2d_batch_run(conv2d_batch_t batch, const float *const *d_in, const float *const *d_f,
                      float *const *d_out, void *stream);
 
 /* Groups of a batch: their count, the total tile count, and for the first
  * `cap` groups the filter size (filt[2g], filt[2g+1]), configuration and
- * persistent grid size (groups of one multi-filter kernel share its grid), in
- * launch and tile-list order. Any output pointer may be NULL. */
+ * persistent grid size. Any output pointer may be NULL. */
 int conv2d_batch_info(conv2d_batch_t batch, int *n_groups, int *total_tiles, int *filt,
                       conv2d_config *cfgs, int *grids, int cap);
 
@@ -222,9 +211,8 @@ int conv2d_compile_batch(conv2d_shape s, const conv2d_config *cfg, char *path_ou
  * and filter are generated on the device from its seeds (the recipe of
  * conv2d_fill_uniform), standing in for an image that arrives in HBM. When
  * one of `streams` streams is free, every admitted request not yet launched
- * (up to max_batch) is launched as one batch: one fill launch, then the
- * multi-filter kernel of conv2d_batch_run's default path (built at start-up
- * for the trace's filter sizes) over the batch's tiles.
+ * (up to max_batch) is launched as one batch: one fill launch, then one
+ * persistent batched kernel per filter size present (as in conv2d_batch_run).
  * Batches on different streams overlap on the device. A request's latency
  * runs from its arrival time to the host observing its batch's completion
  * event; outputs stay on the device. serial_plain = 1 runs the same trace one

@@ -272,7 +272,7 @@ def conv2d_benchmark(s: Shape, cfg, warmup: int = 2, reps: int = 20, flush_mall:
     return med.value, mn.value
 
 
-CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK, CONV2D_BATCH_PER_GROUP = 1, 2, 4
+CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK = 1, 2
 
 for _name, (_res, _args) in {
     "conv2d_batch_plan": (c_int, [P(c_void_p), c_int, P(Shape), c_int]),

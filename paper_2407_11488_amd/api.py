@@ -162,7 +162,7 @@ class Hotspot:
             pass
 
 
-def hotspot_reference(temp, power, steps, coeffs, out=None, stream=None):
+def reference_hotspot(temp, power, steps, coeffs, out=None, stream=None):
     """The library's one-step-per-launch hotspot reference."""
     torch = _torch()
     rows, cols = temp.shape

@@ -9,8 +9,6 @@
 // changed since the last run).
 #include <algorithm>
 #include <climits>
-#include <cstdio>
-#include <fstream>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -57,18 +55,6 @@ struct conv2d_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::mutex mu;
-    // Multi-filter path: kernels of at most kMaxMultiGroups filter groups
-    // each, run one after another, each over its own slice of the tile list
-    // with its own pair of tile counters.
-    struct Multi {
-        MultiKernel mk;
-        int grid = 0;
-        size_t desc_begin = 0, owner_begin = 0;
-        int tiles = 0;
-        int* counters = nullptr;   // into d_counters
-    };
-    std::vector<Multi> multi;
-    int* d_counters = nullptr;
 };
 
 static void batch_free(conv2d_batch_s* b)
@@ -81,8 +67,6 @@ static void batch_free(conv2d_batch_s* b)
         hipEventDestroy(b->copied);
     }
     for (auto& g : b->groups) unload_module(&g.mod);
-    for (auto& m : b->multi) unload_module(&m.mk.mod);
-    if (b->d_counters) hipFree(b->d_counters);
     if (b->h_desc) hipHostFree(b->h_desc);
     if (b->d_desc) hipFree(b->d_desc);
     if (b->d_owner) hipFree(b->d_owner);
@@ -92,42 +76,6 @@ static void batch_free(conv2d_batch_s* b)
 static int launch_group(const Group& g, hipStream_t st)
 {
     return launch_batch_kernel(g.mod, g.cfg, g.grid, g.a_desc, g.a_owner, g.a_total, st);
-}
-
-static int launch_multi(const conv2d_batch_s* b, hipStream_t st)
-{
-    for (const auto& m : b->multi) {
-        int rc = launch_multi_kernel(m.mk, m.grid, b->d_desc + m.desc_begin, b->d_owner + m.owner_begin, m.tiles,
-                                     m.counters, st);
-        if (rc) return rc;
-    }
-    return CONV2D_OK;
-}
-
-// Captures the multi-filter kernels, in order, as one graph.
-static int capture_multi(conv2d_batch_s* b)
-{
-    hipStream_t st = nullptr;
-    CONV2D_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) {
-        hipStreamDestroy(st);
-        return hip_fail(e, "hipStreamBeginCapture");
-    }
-    int rc = launch_multi(b, st);
-    hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(st, &graph);
-    if (rc == CONV2D_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
-    if (rc == CONV2D_OK) {
-        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
-    }
-    if (graph) {
-        if (rc == CONV2D_OK) b->graph = graph;
-        else hipGraphDestroy(graph);
-    }
-    hipStreamDestroy(st);
-    return rc;
 }
 
 // Captures every group's kernel as a parallel branch of one graph.
@@ -208,101 +156,6 @@ int launch_batch_kernel(const Module& m, const conv2d_config& cfg, int grid, con
     return CONV2D_OK;
 }
 
-// Fastest point with kMultiThreads threads in a tuner result database.
-static bool best_multi_point(const std::string& path, const std::string& arch, const conv2d_shape& s,
-                             conv2d_config* c)
-{
-    std::ifstream f(path);
-    if (!f) return false;
-    bool found = false;
-    double best = 0;
-    std::string line;
-    while (std::getline(f, line)) {
-        JsonObj o;
-        if (!json_parse_line(line, &o) || o.str["arch"] != arch || o.str["status"] != "ok") continue;
-        auto sh = o.arr.find("shape"), cf = o.arr.find("config");
-        if (sh == o.arr.end() || cf == o.arr.end() || sh->second.size() != 4 || cf->second.size() != 7) continue;
-        const auto& a = sh->second;
-        if ((int)a[0] != s.out_h || (int)a[1] != s.out_w || (int)a[2] != s.filt_h || (int)a[3] != s.filt_w) continue;
-        const auto& v = cf->second;
-        if ((int)v[0] * (int)v[1] != kMultiThreads) continue;
-        const double ms = o.num["ms"];
-        if (ms > 0 && (!found || ms < best)) {
-            *c = conv2d_config{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], (int)v[6]};
-            best = ms;
-            found = true;
-        }
-    }
-    return found;
-}
-
-conv2d_config multi_config_for_filter(const DeviceInfo& dev, int fh, int fw)
-{
-    std::string wp = env_str("CONV2D_WINNERS");
-    if (wp.empty()) wp = winners_default_path();
-    const conv2d_shape ts{4096, 4096, fh, fw};
-    conv2d_config c{};
-    bool ok = cache_lookup_filter(wp, dev.arch, fh, fw, ts, &c) == CONV2D_OK &&
-              c.block_x * c.block_y == kMultiThreads;
-    if (!ok) {
-        const size_t k = wp.find_last_of('/');
-        const std::string dir = k == std::string::npos ? std::string(".") : wp.substr(0, k);
-        char name[128];
-        std::snprintf(name, sizeof name, "/results_%s_4096x4096_%dx%d.jsonl", dev.arch.c_str(), fh, fw);
-        ok = best_multi_point(dir + name, dev.arch, ts, &c);
-    }
-    if (!ok) c = conv2d_config{16, 16, 1, 1, 1, 0, 1};
-    c.filter_in_const = 0;
-    c.unroll = 1;   // rolled row loop: the groups share one register budget
-    if (conv2d_config_check(ts, &c, dev.lds_limit) != CONV2D_OK) c = conv2d_config{16, 16, 1, 1, 0, 0, 1};
-    clear_error();
-    return c;
-}
-
-int build_multi_kernel(const DeviceInfo& dev, const std::vector<std::pair<int, int>>& filters, MultiKernel* mk)
-{
-    unload_module(&mk->mod);
-    mk->groups.clear();
-    for (const auto& f : filters) mk->groups.push_back(MultiGroup{f.first, f.second, multi_config_for_filter(dev, f.first, f.second)});
-    // Costliest tile first: the tile list is walked in this order, so the
-    // last tiles claimed are the cheapest.
-    auto cost = [](const MultiGroup& g) {
-        return (long long)g.fh * g.fw * g.cfg.block_x * g.cfg.tile_x * g.cfg.block_y * g.cfg.tile_y;
-    };
-    std::sort(mk->groups.begin(), mk->groups.end(), [&](const MultiGroup& a, const MultiGroup& c) {
-        if (cost(a) != cost(c)) return cost(a) > cost(c);
-        if (a.fh * a.fw != c.fh * c.fw) return a.fh * a.fw > c.fh * c.fw;
-        return a.fh > c.fh;
-    });
-    std::vector<char> code;
-    int rc = compile_source(multi_options(kMultiThreads, mk->groups, dev.arch), "multi-filter kernel", &code, nullptr);
-    if (rc) return rc;
-    rc = load_module(code, multi_kernel_name(mk->groups), &mk->mod);
-    if (rc) return rc;
-    int per_cu = 0;
-    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mk->mod.fn, kMultiThreads, 0) != hipSuccess ||
-        per_cu < 1) {
-        (void)hipGetLastError();
-        per_cu = 1;
-    }
-    mk->grid_cap = per_cu * dev.cus;
-    return CONV2D_OK;
-}
-
-int launch_multi_kernel(const MultiKernel& mk, int grid, const void* d_desc, const void* d_owner, int total_tiles,
-                        int* d_counters, hipStream_t st)
-{
-    if (grid < 1 || grid > total_tiles) return fail(CONV2D_EINVAL, "multi-filter launch: grid outside [1, tiles]");
-    const void* d = d_desc;
-    const void* o = d_owner;
-    int total = total_tiles;
-    int* c = d_counters;
-    void* args[] = {&d, &o, &total, &c};
-    hipError_t e = hipModuleLaunchKernel(mk.mod.fn, (unsigned)grid, 1, 1, kMultiThreads, 1, 1, 0, st, args, nullptr);
-    if (e != hipSuccess) return fail(CONV2D_ELAUNCH, std::string("multi-filter launch: ") + hipGetErrorString(e));
-    return CONV2D_OK;
-}
-
 }  // namespace conv2d
 
 extern "C" int conv2d_batch_plan(conv2d_batch_t* out, int n, const conv2d_shape* shapes, int flags)
@@ -325,107 +178,58 @@ extern "C" int conv2d_batch_plan(conv2d_batch_t* out, int n, const conv2d_shape*
     b->flags = flags;
     b->shapes.assign(shapes, shapes + n);
 
+    // Group by filter size, heaviest filters first.
     std::map<std::pair<int, int>, std::vector<int>> by_filter;
     for (int i = 0; i < n; ++i) by_filter[{shapes[i].filt_h, shapes[i].filt_w}].push_back(i);
+    std::vector<std::pair<int, int>> keys;
+    for (auto& kv : by_filter) keys.push_back(kv.first);
+    std::sort(keys.begin(), keys.end(), [](auto a, auto c) { return a.first * a.second > c.first * c.second; });
+
     std::vector<unsigned short> owner;
     std::vector<ConvDesc> proto;
     b->desc_slot.assign(n, -1);
-    // Appends problem p's descriptor (tile numbers from tile_begin on) and its
-    // tile owners; `local` is its index among the descriptors of one launch.
-    auto add_problem = [&](int p, const conv2d_config& cfg, int group, int tile_begin, int local) {
-        const conv2d_shape& s = shapes[p];
-        Geometry geo = geometry(s.out_h, s.out_w, cfg);
-        ConvDesc d{};
-        d.H = s.out_h;
-        d.W = s.out_w;
-        d.tiles_x = geo.tiles_x;
-        d.tile_begin = tile_begin;
-        d.in_bytes = (unsigned)(4ull * (s.out_h + s.filt_h - 1) * (s.out_w + s.filt_w - 1));
-        d.n_tiles = geo.n_tiles;
-        d.group = group;
-        owner.insert(owner.end(), (size_t)geo.n_tiles, (unsigned short)local);
-        b->desc_slot[p] = (int)proto.size();
-        proto.push_back(d);
-        return geo.n_tiles;
-    };
-
-    if (!(flags & CONV2D_BATCH_PER_GROUP)) {
-        // One multi-filter kernel per kMaxMultiGroups filter sizes.
-        std::vector<std::pair<int, int>> filters;
-        for (auto& kv : by_filter) filters.push_back(kv.first);
-        for (size_t f0 = 0; f0 < filters.size(); f0 += kMaxMultiGroups) {
-            conv2d_batch_s::Multi m;
-            const std::vector<std::pair<int, int>> part(
-                filters.begin() + f0, filters.begin() + std::min(filters.size(), f0 + kMaxMultiGroups));
-            rc = build_multi_kernel(b->dev, part, &m.mk);
-            if (rc) {
-                unload_module(&m.mk.mod);
-                return rc;
-            }
-            m.desc_begin = proto.size();
-            m.owner_begin = owner.size();
-            long long tiles = 0;
-            int local = 0;
-            for (size_t g = 0; g < m.mk.groups.size(); ++g) {
-                const MultiGroup& mg = m.mk.groups[g];
-                for (int p : by_filter[{mg.fh, mg.fw}]) {
-                    tiles += add_problem(p, mg.cfg, (int)g, (int)tiles, local++);
-                    if (tiles > INT_MAX) {
-                        unload_module(&m.mk.mod);
-                        return fail(CONV2D_EINVAL, "batch: too many tiles in one launch");
-                    }
-                }
-            }
-            m.tiles = (int)tiles;
-            m.grid = std::max(1, std::min(m.tiles, m.mk.grid_cap));
-            b->multi.push_back(std::move(m));
+    for (const auto& key : keys) {
+        Group g;
+        g.fh = key.first;
+        g.fw = key.second;
+        g.problems = by_filter[key];
+        rc = batch_module_for_filter(b->dev, g.fh, g.fw, &g.cfg, &g.mod);
+        if (rc) return rc;
+        g.threads = g.cfg.block_x * g.cfg.block_y;
+        g.desc_begin = proto.size();
+        g.owner_begin = owner.size();
+        for (size_t k = 0; k < g.problems.size(); ++k) {
+            const conv2d_shape& s = shapes[g.problems[k]];
+            Geometry geo = geometry(s.out_h, s.out_w, g.cfg);
+            ConvDesc d{};
+            d.H = s.out_h;
+            d.W = s.out_w;
+            d.tiles_x = geo.tiles_x;
+            d.tile_begin = g.total_tiles;
+            d.in_bytes = (unsigned)(4ull * (s.out_h + s.filt_h - 1) * (s.out_w + s.filt_w - 1));
+            d.n_tiles = geo.n_tiles;
+            if ((long long)g.total_tiles + geo.n_tiles > INT_MAX)
+                return fail(CONV2D_EINVAL, "batch: too many tiles in one filter group");
+            g.total_tiles += geo.n_tiles;
+            owner.insert(owner.end(), (size_t)geo.n_tiles, (unsigned short)k);
+            b->desc_slot[g.problems[k]] = (int)proto.size();
+            proto.push_back(d);
         }
-    } else {
-        // One persistent kernel per filter size, heaviest filters first.
-        std::vector<std::pair<int, int>> keys;
-        for (auto& kv : by_filter) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end(), [](auto a, auto c) { return a.first * a.second > c.first * c.second; });
-        for (const auto& key : keys) {
-            Group g;
-            g.fh = key.first;
-            g.fw = key.second;
-            g.problems = by_filter[key];
-            rc = batch_module_for_filter(b->dev, g.fh, g.fw, &g.cfg, &g.mod);
-            if (rc) return rc;
-            g.threads = g.cfg.block_x * g.cfg.block_y;
-            g.desc_begin = proto.size();
-            g.owner_begin = owner.size();
-            long long tiles = 0;
-            for (size_t k = 0; k < g.problems.size(); ++k) {
-                tiles += add_problem(g.problems[k], g.cfg, 0, (int)tiles, (int)k);
-                if (tiles > INT_MAX) return fail(CONV2D_EINVAL, "batch: too many tiles in one filter group");
-            }
-            g.total_tiles = (int)tiles;
-            int per_cu = 0;
-            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g.mod.fn, g.threads, 0) != hipSuccess ||
-                per_cu < 1)
-                per_cu = 1;
-            g.grid = std::max(8, std::min(g.total_tiles, per_cu * b->dev.cus));
-            b->groups.push_back(std::move(g));
-        }
+        int per_cu = 0;
+        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g.mod.fn, g.threads, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        g.grid = std::max(8, std::min(g.total_tiles, per_cu * b->dev.cus));
+        b->groups.push_back(std::move(g));
     }
 
-    // Device tables: descriptors (pointers filled at run time), tile owners,
-    // and the multi-filter kernels' tile counters (zero between launches).
+    // Device tables: descriptors (pointers filled at run time) and tile owners.
     if (hipHostMalloc((void**)&b->h_desc, sizeof(ConvDesc) * n, hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&b->d_desc, sizeof(ConvDesc) * n) != hipSuccess ||
         hipMalloc((void**)&b->d_owner, sizeof(unsigned short) * owner.size()) != hipSuccess)
         return fail(CONV2D_ENOMEM, "batch: allocation of the descriptor tables failed");
     std::memcpy(b->h_desc, proto.data(), sizeof(ConvDesc) * n);
     CONV2D_HIP(hipMemcpy(b->d_owner, owner.data(), sizeof(unsigned short) * owner.size(), hipMemcpyHostToDevice));
-    if (!b->multi.empty()) {
-        const size_t nc = 2 * b->multi.size();
-        if (hipMalloc((void**)&b->d_counters, sizeof(int) * nc) != hipSuccess)
-            return fail(CONV2D_ENOMEM, "batch: allocation of the tile counters failed");
-        CONV2D_HIP(hipMemset(b->d_counters, 0, sizeof(int) * nc));
-        CONV2D_HIP(hipDeviceSynchronize());
-        for (size_t k = 0; k < b->multi.size(); ++k) b->multi[k].counters = b->d_counters + 2 * k;
-    }
     CONV2D_HIP(hipEventCreateWithFlags(&b->copied, hipEventDisableTiming));
     for (auto& g : b->groups) {
         g.a_desc = b->d_desc + g.desc_begin;
@@ -433,7 +237,7 @@ extern "C" int conv2d_batch_plan(conv2d_batch_t* out, int n, const conv2d_shape*
         g.a_total = g.total_tiles;
     }
     if (!(flags & CONV2D_BATCH_NO_GRAPH)) {
-        rc = b->multi.empty() ? capture(b.get()) : capture_multi(b.get());
+        rc = capture(b.get());
         if (rc) return rc;
     }
     *out = b.release();
@@ -491,7 +295,6 @@ extern "C" int conv2d_batch_run(conv2d_batch_t b, const float* const* d_in, cons
         if (e != hipSuccess) return fail(CONV2D_ELAUNCH, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         return CONV2D_OK;
     }
-    if (!b->multi.empty()) return launch_multi(b, st);
     for (const auto& g : b->groups) {
         int rc = launch_group(g, st);
         if (rc) return rc;
@@ -504,24 +307,16 @@ extern "C" int conv2d_batch_info(conv2d_batch_t b, int* n_groups, int* total_til
 {
     clear_error();
     if (!b) return fail(CONV2D_EINVAL, "batch is NULL");
-    int tiles = 0, ng = 0;
-    auto put = [&](int fh, int fw, const conv2d_config& c, int grid) {
-        if (ng < cap) {
-            if (filt) { filt[2 * ng] = fh; filt[2 * ng + 1] = fw; }
-            if (cfgs) cfgs[ng] = c;
-            if (grids) grids[ng] = grid;
+    int tiles = 0;
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        tiles += b->groups[g].total_tiles;
+        if ((int)g < cap) {
+            if (filt) { filt[2 * g] = b->groups[g].fh; filt[2 * g + 1] = b->groups[g].fw; }
+            if (cfgs) cfgs[g] = b->groups[g].cfg;
+            if (grids) grids[g] = b->groups[g].grid;
         }
-        ++ng;
-    };
-    for (const auto& m : b->multi) {
-        tiles += m.tiles;
-        for (const auto& g : m.mk.groups) put(g.fh, g.fw, g.cfg, m.grid);
     }
-    for (const auto& g : b->groups) {
-        tiles += g.total_tiles;
-        put(g.fh, g.fw, g.cfg, g.grid);
-    }
-    if (n_groups) *n_groups = ng;
+    if (n_groups) *n_groups = (int)b->groups.size();
     if (total_tiles) *total_tiles = tiles;
     return CONV2D_OK;
 }

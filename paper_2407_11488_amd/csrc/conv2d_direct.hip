@@ -46,10 +46,8 @@
 #define CONV_BATCH 0
 #endif
 
-#if CONV_BATCH != 2
 #ifndef CONV_BX
 #error "CONV_BX must be defined"
-#endif
 #endif
 
 #ifndef CONV_NAME
@@ -270,7 +268,7 @@ CONV_NAME(const float* __restrict__ in, const float* __restrict__ filt,
 }
 #else
 #if CONV_FCONST
-#error "the batched kernels read each problem's own filter through its pointer"
+#error "the batched kernel reads each problem's own filter through its pointer"
 #endif
 // One problem of a batch, as the host library lays it out in device memory.
 struct ConvDesc {
@@ -282,8 +280,6 @@ struct ConvDesc {
     int tile_begin;   // first tile of this problem in the tile list
     u32 in_bytes;
     int n_tiles;      // tiles of this problem
-    int group;        // filter group (multi-filter kernel)
-    int pad_;
 };
 
 // The descriptor of tile t. The owner is read with a 16-bit vector load (no
@@ -295,7 +291,6 @@ static __device__ __forceinline__ const ConvDesc* tile_desc(const ConvDesc* __re
     return descs + __builtin_amdgcn_readfirstlane((int)owner[t]);
 }
 
-#if CONV_BATCH == 1
 // Many images with the same filter size: a persistent grid (at least 8
 // workgroups) walks the group's tile list. The tiles of XCD x (= workgroup id
 // mod 8) form one contiguous range, shared out by stride among that XCD's
@@ -326,79 +321,4 @@ CONV_NAME(const ConvDesc* __restrict__ descs, const unsigned short* __restrict__
             d->in, d->filt, d->out, d->H, d->W, d->in_bytes, tile_x, tile_y, lds);
     }
 }
-#else
-// Many images with several filter sizes in one persistent kernel.
-//   CONV_NT      threads per workgroup, shared by every group
-//   CONV_GROUPS  one G(k, FH, FW, BX, BY, TX, TY, LDS, UNROLL) per filter
-//                group k = 0, 1, ..., with BX * BY = CONV_NT
-// The tile list holds every group's tiles, costliest group first. A
-// workgroup starts at tile blockIdx.x and then takes the next unclaimed tile
-// from counters[0] (claimed one tile ahead, so the atomic's latency hides
-// behind the current tile), until the list is exhausted; the last workgroup
-// to finish (counted in counters[1]) sets both counters back to 0 for the
-// next launch. Input and output rows are accessed a float at a time (any
-// width, any alignment).
-#define G(k, fh, fw, bx, by, tx, ty, lds, unr) \
-    static_assert((bx) * (by) == CONV_NT, "every group of the multi-filter kernel has CONV_NT threads");
-CONV_GROUPS
-#undef G
-
-static constexpr int lds_floats_max()
-{
-    int m = 4;
-#define G(k, fh, fw, bx, by, tx, ty, lds, unr) \
-    m = m > Geo<fh, fw, bx, by, tx, ty, lds, unr, 1, 1>::LDS_FLOATS ? m : Geo<fh, fw, bx, by, tx, ty, lds, unr, 1, 1>::LDS_FLOATS;
-    CONV_GROUPS
-#undef G
-    return m;
-}
-
-extern "C" __global__ void __launch_bounds__(CONV_NT)
-CONV_NAME(const ConvDesc* __restrict__ descs, const unsigned short* __restrict__ owner, int total_tiles,
-          int* __restrict__ counters)
-{
-    __shared__ __attribute__((aligned(16))) float lds[lds_floats_max()];
-    __shared__ int next_tile[2];
-    int t = (int)blockIdx.x;
-    int parity = 0;
-    while (t < total_tiles) {
-        int claimed = 0;
-        if (threadIdx.x == 0)
-            claimed = (int)gridDim.x + atomicAdd(&counters[0], 1);
-        const ConvDesc* d = tile_desc(descs, owner, t);
-        const int lt = t - d->tile_begin;
-        if ((unsigned)lt < (unsigned)d->n_tiles) {   // else inconsistent tables: skip (uniform)
-            const int tile_y = lt / d->tiles_x;
-            const int tile_x = lt - tile_y * d->tiles_x;
-            switch (__builtin_amdgcn_readfirstlane(d->group)) {
-#define G(k, fh, fw, bx, by, tx, ty, lds_, unr) \
-            case k: \
-                conv_tile<fh, fw, bx, by, tx, ty, lds_, unr, 1, 1>(d->in, d->filt, d->out, d->H, d->W, d->in_bytes, \
-                                                                  tile_x, tile_y, lds); \
-                break;
-                CONV_GROUPS
-#undef G
-            default:
-                break;
-            }
-        }
-        // One barrier per tile: it publishes the next tile and tells every
-        // thread that the LDS tile is free again. The two slots alternate, so
-        // a slot is rewritten only after every thread has passed the barrier
-        // that follows its last read.
-        if (threadIdx.x == 0)
-            next_tile[parity] = claimed;
-        __syncthreads();
-        t = next_tile[parity];
-        parity ^= 1;
-    }
-    if (threadIdx.x == 0) {
-        if (atomicAdd(&counters[1], 1) == (int)gridDim.x - 1) {
-            // Every other workgroup has finished claiming tiles.
-            atomicExch(&counters[0], 0);
-            atomicExch(&counters[1], 0);
-        }
-    }
-}
-#endif
 #endif

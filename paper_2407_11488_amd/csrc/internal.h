@@ -63,9 +63,6 @@ std::vector<std::string> direct_options(const conv2d_shape& s, const conv2d_conf
 // Returns CONV2D_OK or CONV2D_ECOMPILE. Thread safe.
 int compile_program(const std::string& source, const char* name, const std::vector<std::string>& opts,
                     const std::string& what, std::vector<char>* code, std::string* path);
-// compile_program of the convolution kernel source.
-int compile_source(const std::vector<std::string>& opts, const std::string& what, std::vector<char>* code,
-                   std::string* path);
 // Compile (or read from the disk cache) the code object for a configuration.
 // Returns CONV2D_OK or CONV2D_ECOMPILE. Thread safe.
 int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int vout,
@@ -129,7 +126,7 @@ int launch_count_mismatch(const float* a, const float* b, size_t n, unsigned* d_
 int launch_flush(float* d, size_t n, hipStream_t stream);
 
 // ---------------------------------------------------------------- batched kernels
-// Mirror of the batched kernels' ConvDesc (conv2d_direct.hip, CONV_BATCH=1, 2).
+// Mirror of the batched kernel's ConvDesc (conv2d_direct.hip, CONV_BATCH=1).
 struct ConvDesc {
     const float* in;
     const float* filt;
@@ -139,47 +136,8 @@ struct ConvDesc {
     int tile_begin;
     unsigned in_bytes;
     int n_tiles;
-    int group;      // filter group of the multi-filter kernel
-    int pad_;
 };
-static_assert(sizeof(ConvDesc) == 56, "descriptor layout must match the kernel");
-
-// One filter group of the multi-filter batched kernel (CONV_BATCH=2).
-struct MultiGroup {
-    int fh = 0, fw = 0;
-    conv2d_config cfg{};
-};
-// Workgroup size shared by every group of the multi-filter kernel.
-constexpr int kMultiThreads = 256;
-// Filter sizes per multi-filter kernel (more are split over several kernels).
-constexpr size_t kMaxMultiGroups = 8;
-// The multi-filter kernel for a set of filter sizes: its groups, costliest
-// tile first (the order of the tile list), and the resident workgroup count.
-struct MultiKernel {
-    Module mod;
-    std::vector<MultiGroup> groups;
-    int grid_cap = 0;
-    int group_of(int fh, int fw) const
-    {
-        for (size_t k = 0; k < groups.size(); ++k)
-            if (groups[k].fh == fh && groups[k].fw == fw) return (int)k;
-        return -1;
-    }
-};
-std::string multi_kernel_name(const std::vector<MultiGroup>& groups);
-std::vector<std::string> multi_options(int nt, const std::vector<MultiGroup>& groups, const std::string& arch);
-// The configuration of a filter size inside the multi-filter kernel: the
-// tuned winner when it has kMultiThreads threads, else the fastest such point
-// of the tuner's result database for that filter at 4096x4096 (next to the
-// winners cache), else the default shape; filter read through its pointer,
-// rolled row loop.
-conv2d_config multi_config_for_filter(const DeviceInfo& dev, int fh, int fw);
-// Builds (compiles, loads, sizes) the multi-filter kernel for `filters`.
-int build_multi_kernel(const DeviceInfo& dev, const std::vector<std::pair<int, int>>& filters, MultiKernel* mk);
-// Launches it over `total_tiles` tiles on `grid` workgroups. d_counters holds
-// two ints that are 0 before the launch and are 0 again after it.
-int launch_multi_kernel(const MultiKernel& mk, int grid, const void* d_desc, const void* d_owner, int total_tiles,
-                        int* d_counters, hipStream_t st);
+static_assert(sizeof(ConvDesc) == 48, "descriptor layout must match the kernel");
 
 // The tuned configuration for a filter size (4096x4096 entry of the winners
 // cache, else any entry with that filter, else the default; filter always read

@@ -112,50 +112,11 @@ int compile_program(const std::string& source, const char* name, const std::vect
     return CONV2D_OK;
 }
 
-int compile_source(const std::vector<std::string>& opts, const std::string& what, std::vector<char>* code,
-                   std::string* path)
-{
-    return compile_program(direct_source(), "conv2d_direct.hip", opts, what, code, path);
-}
-
 int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int vout,
                    const std::string& arch, std::vector<char>* code, std::string* path, bool batch)
 {
-    return compile_source(direct_options(s, c, vin, vout, arch, batch), "config " + config_str(c), code, path);
-}
-
-std::string multi_kernel_name(const std::vector<MultiGroup>& groups)
-{
-    std::string n = "conv2d_multi";
-    for (const auto& g : groups) {
-        char b[96];
-        std::snprintf(b, sizeof b, "_f%dx%d_b%dx%d_t%dx%d_l%du%d", g.fh, g.fw, g.cfg.block_x, g.cfg.block_y,
-                      g.cfg.tile_x, g.cfg.tile_y, g.cfg.use_lds, g.cfg.unroll);
-        n += b;
-    }
-    return n;
-}
-
-std::vector<std::string> multi_options(int nt, const std::vector<MultiGroup>& groups, const std::string& arch)
-{
-    std::string list;
-    for (size_t k = 0; k < groups.size(); ++k) {
-        const MultiGroup& g = groups[k];
-        char b[128];
-        std::snprintf(b, sizeof b, "G(%zu,%d,%d,%d,%d,%d,%d,%d,%d)", k, g.fh, g.fw, g.cfg.block_x, g.cfg.block_y,
-                      g.cfg.tile_x, g.cfg.tile_y, g.cfg.use_lds, g.cfg.unroll);
-        list += b;
-    }
-    return {
-        "--offload-arch=" + arch,
-        "-O3",
-        "-std=c++17",
-        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-DCONV_BATCH=2",
-        "-DCONV_NT=" + std::to_string(nt),
-        "-DCONV_GROUPS=" + list,
-        "-DCONV_NAME=" + multi_kernel_name(groups),
-    };
+    return compile_program(direct_source(), "conv2d_direct.hip", direct_options(s, c, vin, vout, arch, batch),
+                           "config " + config_str(c), code, path);
 }
 
 int load_module(const std::vector<char>& code, const std::string& kernel, Module* m)

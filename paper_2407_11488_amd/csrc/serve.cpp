@@ -7,8 +7,7 @@
 // in for an image that arrives in HBM). Whenever one of K streams is free, all
 // admitted requests not yet launched (up to max_batch) go out as one batch:
 // one fill launch for every image and filter of the batch, then one
-// persistent multi-filter kernel (built at start-up for the trace's filter
-// sizes; the batched path's kernel) over the batch's tiles. Batches on different
+// persistent batched kernel per filter size present. Batches on different
 // streams overlap on the device; completion is observed with events, and each
 // request's latency runs from its arrival to the host seeing its batch done.
 //
@@ -22,7 +21,6 @@
 #include <map>
 #include <memory>
 #include <numeric>
-#include <set>
 #include <tuple>
 #include <thread>
 
@@ -96,6 +94,11 @@ struct Req {
     bool stalled = false;
 };
 
+struct FilterKernel {
+    conv2d_config cfg{};
+    Module mod;
+    int grid_cap = 0;     // resident workgroups on the whole GPU
+};
 
 struct Slot {
     hipStream_t st = nullptr;
@@ -105,7 +108,6 @@ struct Slot {
     char* h_tab = nullptr;   // pinned: [fill descs | conv descs | owners]
     char* d_tab = nullptr;
     size_t cap = 0;
-    int* d_counters = nullptr;   // two per multi-filter kernel, 0 between launches
 };
 
 double percentile(std::vector<double> v, double p)
@@ -129,9 +131,8 @@ public:
             if (s.st) hipStreamDestroy(s.st);
             if (s.h_tab) hipHostFree(s.h_tab);
             if (s.d_tab) hipFree(s.d_tab);
-            if (s.d_counters) hipFree(s.d_counters);
         }
-        for (auto& mk : kernels_) unload_module(&mk.mod);
+        for (auto& kv : kernels_) unload_module(&kv.second.mod);
         for (auto& kv : direct_) unload_module(&kv.second);
     }
 
@@ -141,7 +142,6 @@ public:
         if (rc) return rc;
         req_.assign(n_, Req{});
         size_t max_tiles_per_req = 1;
-        std::set<std::pair<int, int>> filters;
         for (int i = 0; i < n_; ++i) {
             const conv2d_shape& s = rq_[i].shape;
             rc = shape_check(s);
@@ -156,26 +156,22 @@ public:
                 return fail(CONV2D_EINVAL, "request " + std::to_string(i) + " alone exceeds the HBM budget");
             if (i > 0 && rq_[i].arrival_s < rq_[i - 1].arrival_s)
                 return fail(CONV2D_EINVAL, "arrival times must be non-decreasing");
-            filters.insert({s.filt_h, s.filt_w});
-        }
-        // The multi-filter kernels for every filter size of the trace are
-        // built up front (at most kMaxMultiGroups sizes per kernel).
-        if (!o_.serial_plain) {
-            const std::vector<std::pair<int, int>> fl(filters.begin(), filters.end());
-            for (size_t f0 = 0; f0 < fl.size(); f0 += kMaxMultiGroups) {
-                kernels_.emplace_back();
-                const std::vector<std::pair<int, int>> part(fl.begin() + f0,
-                                                            fl.begin() + std::min(fl.size(), f0 + kMaxMultiGroups));
-                rc = build_multi_kernel(dev_, part, &kernels_.back());
+            // Kernels for every filter size of the trace are built up front.
+            const auto key = std::make_pair(s.filt_h, s.filt_w);
+            if (!o_.serial_plain && !kernels_.count(key)) {
+                FilterKernel fk;
+                rc = batch_module_for_filter(dev_, s.filt_h, s.filt_w, &fk.cfg, &fk.mod);
                 if (rc) return rc;
-                for (size_t g = 0; g < kernels_.back().groups.size(); ++g)
-                    where_[{kernels_.back().groups[g].fh, kernels_.back().groups[g].fw}] = {(int)kernels_.size() - 1,
-                                                                                            (int)g};
+                int per_cu = 0;
+                if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fk.mod.fn,
+                                                                       fk.cfg.block_x * fk.cfg.block_y, 0) != hipSuccess ||
+                    per_cu < 1)
+                    per_cu = 1;
+                fk.grid_cap = per_cu * dev_.cus;
+                kernels_.emplace(key, fk);
             }
-            for (int i = 0; i < n_; ++i) {
-                const conv2d_shape& s = rq_[i].shape;
-                const auto w = where_.at({s.filt_h, s.filt_w});
-                const conv2d_config& c = kernels_[w.first].groups[w.second].cfg;
+            if (!o_.serial_plain) {
+                const conv2d_config& c = kernels_[key].cfg;
                 max_tiles_per_req = std::max(max_tiles_per_req, (size_t)geometry(s.out_h, s.out_w, c).n_tiles);
             }
         }
@@ -203,14 +199,7 @@ public:
             if (hipHostMalloc((void**)&s.h_tab, s.cap, hipHostMallocDefault) != hipSuccess ||
                 hipMalloc((void**)&s.d_tab, s.cap) != hipSuccess)
                 return fail(CONV2D_ENOMEM, "serve: descriptor tables");
-            if (!kernels_.empty()) {
-                const size_t nc = 2 * kernels_.size();
-                if (hipMalloc((void**)&s.d_counters, nc * sizeof(int)) != hipSuccess)
-                    return fail(CONV2D_ENOMEM, "serve: tile counters");
-                CONV2D_HIP(hipMemset(s.d_counters, 0, nc * sizeof(int)));
-            }
         }
-        CONV2D_HIP(hipDeviceSynchronize());
         return CONV2D_OK;
     }
 
@@ -302,39 +291,32 @@ private:
             fill[2 * k + 1] = FillDesc{r.f, r.n_f, rq_[batch[k]].seed_f, 0};
             max_n = std::max<unsigned long long>(max_n, r.n_in);
         }
-        // Descriptors and owners in tile-list order: kernel by kernel, and
-        // within a kernel group by group (costliest tile first).
-        struct L {
-            size_t d0, o0;
+        struct G {
+            const FilterKernel* fk;
+            size_t d0, dn, o0;
             int tiles;
         };
-        std::vector<L> launches(kernels_.size(), L{0, 0, 0});
-        std::vector<std::vector<std::vector<int>>> by_group(kernels_.size());
-        for (size_t m = 0; m < kernels_.size(); ++m) by_group[m].resize(kernels_[m].groups.size());
-        for (int i : batch) {
-            const auto w = where_.at({rq_[i].shape.filt_h, rq_[i].shape.filt_w});
-            by_group[w.first][w.second].push_back(i);
-        }
+        std::vector<G> groups;
+        std::map<std::pair<int, int>, std::vector<int>> by_filter;
+        for (int i : batch) by_filter[{rq_[i].shape.filt_h, rq_[i].shape.filt_w}].push_back(i);
         size_t nd = 0, no = 0;
-        for (size_t m = 0; m < kernels_.size(); ++m) {
-            L& l = launches[m];
-            l.d0 = nd;
-            l.o0 = no;
-            int local = 0;
-            for (size_t g = 0; g < by_group[m].size(); ++g) {
-                const conv2d_config& c = kernels_[m].groups[g].cfg;
-                for (int i : by_group[m][g]) {
-                    const conv2d_shape& sh = rq_[i].shape;
-                    const Req& r = req_[i];
-                    Geometry geo = geometry(sh.out_h, sh.out_w, c);
-                    ConvDesc& d = desc[nd++];
-                    d = ConvDesc{r.in, r.f, r.out, sh.out_h, sh.out_w, geo.tiles_x, l.tiles, (unsigned)(r.n_in * 4),
-                                 geo.n_tiles, (int)g, 0};
-                    std::fill(owner + no, owner + no + geo.n_tiles, (unsigned short)local++);
-                    no += geo.n_tiles;
-                    l.tiles += geo.n_tiles;
-                }
+        for (auto& kv : by_filter) {
+            const FilterKernel& fk = kernels_.at(kv.first);
+            G g{&fk, nd, kv.second.size(), no, 0};
+            for (size_t k = 0; k < kv.second.size(); ++k) {
+                const int i = kv.second[k];
+                const conv2d_shape& sh = rq_[i].shape;
+                const Req& r = req_[i];
+                Geometry geo = geometry(sh.out_h, sh.out_w, fk.cfg);
+                ConvDesc& d = desc[nd + k];
+                d = ConvDesc{r.in, r.f, r.out, sh.out_h, sh.out_w, geo.tiles_x, g.tiles, (unsigned)(r.n_in * 4),
+                             geo.n_tiles};
+                std::fill(owner + no, owner + no + geo.n_tiles, (unsigned short)k);
+                no += geo.n_tiles;
+                g.tiles += geo.n_tiles;
             }
+            nd += kv.second.size();
+            groups.push_back(g);
         }
         const size_t bytes = 2 * nb * sizeof(FillDesc) + nb * sizeof(ConvDesc) + no * sizeof(unsigned short);
         if (bytes > s.cap) return fail(CONV2D_EINVAL, "serve: batch tables exceed their capacity");
@@ -345,12 +327,9 @@ private:
             reinterpret_cast<const unsigned short*>(s.d_tab + 2 * nb * sizeof(FillDesc) + nb * sizeof(ConvDesc));
         int rc = launch_fill_uniform_batch(d_fill, (int)(2 * nb), max_n, s.st);
         if (rc) return rc;
-        for (size_t m = 0; m < kernels_.size(); ++m) {
-            const L& l = launches[m];
-            if (l.tiles == 0) continue;
-            const int grid = std::max(1, std::min(l.tiles, kernels_[m].grid_cap));
-            rc = launch_multi_kernel(kernels_[m], grid, d_desc + l.d0, d_owner + l.o0, l.tiles, s.d_counters + 2 * m,
-                                     s.st);
+        for (const G& g : groups) {
+            const int grid = std::max(8, std::min(g.tiles, g.fk->grid_cap));
+            rc = launch_batch_kernel(g.fk->mod, g.fk->cfg, grid, d_desc + g.d0, d_owner + g.o0, g.tiles, s.st);
             if (rc) return rc;
         }
         CONV2D_HIP(hipEventRecord(s.ev, s.st));
@@ -493,9 +472,7 @@ private:
     conv2d_serve_opts o_;
     DeviceInfo dev_;
     std::vector<Req> req_;
-    // deque: a MultiKernel's address stays put while more are added
-    std::deque<MultiKernel> kernels_;
-    std::map<std::pair<int, int>, std::pair<int, int>> where_;   // filter -> (kernel, group)
+    std::map<std::pair<int, int>, FilterKernel> kernels_;
     std::map<std::pair<int, int>, conv2d_config> direct_cfg_;
     std::map<std::tuple<int, int, int, int>, Module> direct_;
     Arena arena_;

@@ -14,6 +14,12 @@ HBM budget. The serial plain capacity is probed first (a trace whose requests
 all arrive at once); the trace then runs at fractions of that rate through the
 continuous-batching server and through the serial plain baseline.
 
+hotspot: the 4096 x 4096 chip workload of the hotspot stencil, 60 steps per
+run, in the plan's configuration (tuned winner when cached) against the
+default configuration.
+
+    python -m paper_2407_11488_amd.workloads hotspot [--reps 20] [--steps 60]
+
 Each prints one JSON line.
 """
 from __future__ import annotations
@@ -83,16 +89,12 @@ def batch_benchmark(reps: int = 20, warmup: int = 3, n: int = 64) -> dict:
 
     b_ms, b_wall = timed(run_batch, reps)
     p_ms, p_wall = timed(run_plain, reps)
-    per_group = Batch(shapes, flags=B.CONV2D_BATCH_PER_GROUP)
-    g_ms, _ = timed(lambda: per_group(ins, fs, outs), reps)
-    per_group.close()
     res = {
         "workload": f"{n} convolutions, sides log-uniform [256, 2048], filters {{3,5,9,17}}",
         "gflop": round(flops / 1e9, 3),
         "batch_ms": round(b_ms, 4), "batch_gflops": round(flops / (b_ms * 1e-3) / 1e9, 1),
         "plain_ms": round(p_ms, 4), "plain_gflops": round(flops / (p_ms * 1e-3) / 1e9, 1),
         "speedup": round(p_ms / b_ms, 3),
-        "per_group_kernels_ms": round(g_ms, 4),
         "batch_wall_ms": round(b_wall, 4), "plain_wall_ms": round(p_wall, 4),
         "groups": batch.info["groups"], "total_tiles": batch.info["total_tiles"],
     }
@@ -147,6 +149,44 @@ def serve_benchmark(duration: float = 60.0, rates=(0.8,), budget_gib: float = 8.
     return out
 
 
+HOTSPOT_FLOP_PER_CELL_STEP = 14
+HOTSPOT_BYTES_PER_CELL_LAUNCH = 12   # read temperature and power, write temperature
+
+
+def hotspot_benchmark(reps: int = 20, warmup: int = 3, steps: int = 60, rows: int = 4096, cols: int = 4096) -> dict:
+    """Times whole runs of `steps` steps (HIP events on the current stream)."""
+    torch = _torch()
+    from .api import Hotspot
+    temp, power, k = datagen.hotspot_problem(rows, cols)
+    td = torch.from_numpy(temp).cuda()
+    pd = torch.from_numpy(power).cuda()
+    out = torch.empty_like(td)
+    st = torch.cuda.current_stream()
+    res = {"workload": f"hotspot chip {rows}x{cols}, {steps} steps", "steps": steps}
+    for name, cfg in (("plan", None), ("default", B.hotspot_default_config().tuple())):
+        plan = Hotspot(rows, cols, cfg)
+        for _ in range(warmup):
+            plan(td, pd, steps, k, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            plan(td, pd, steps, k, out=out)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        launches = -(-steps // plan.config[4])
+        res[name] = {
+            "config": list(plan.config), "source": plan.source, "ms": round(ms, 4),
+            "gflops": round(HOTSPOT_FLOP_PER_CELL_STEP * rows * cols * steps / (ms * 1e-3) / 1e9, 1),
+            "launches": launches, "ms_per_launch": round(ms / launches, 4),
+            "gbs_per_launch": round(HOTSPOT_BYTES_PER_CELL_LAUNCH * rows * cols / (ms / launches * 1e-3) / 1e9, 1),
+        }
+        plan.close()
+    res["tuned_vs_default"] = round(res["default"]["ms"] / res["plan"]["ms"], 3)
+    return res
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -158,9 +198,14 @@ def main(argv=None) -> int:
     s.add_argument("--budget-gib", type=float, default=8.0)
     s.add_argument("--streams", type=int, default=4)
     s.add_argument("--max-batch", type=int, default=64)
+    h = sub.add_parser("hotspot")
+    h.add_argument("--reps", type=int, default=20)
+    h.add_argument("--steps", type=int, default=60)
     a = ap.parse_args(argv)
     if a.cmd == "batch":
         print(json.dumps(batch_benchmark(a.reps)), flush=True)
+    elif a.cmd == "hotspot":
+        print(json.dumps(hotspot_benchmark(a.reps, steps=a.steps)), flush=True)
     else:
         print(json.dumps(serve_benchmark(a.duration, tuple(a.rates), a.budget_gib, a.streams, a.max_batch)),
               flush=True)

@@ -96,7 +96,3 @@ inline void emu_nontemporal_store(T v, T* p)
 
 // Every lane of a workgroup holds the same value wherever the kernels use it.
 inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
-
-// Device-wide integer atomics (the multi-filter batch kernel's tile counter).
-inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
-inline int atomicExch(int* p, int v) { return __atomic_exchange_n(p, v, __ATOMIC_SEQ_CST); }

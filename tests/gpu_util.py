@@ -59,3 +59,29 @@ def vec_class(n):
 def say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def hip_runtime():
+    """The HIP runtime this process already uses (the one torch loaded)."""
+    import ctypes
+    with open("/proc/self/maps") as fh:
+        paths = sorted({ln.split()[-1] for ln in fh if "libamdhip64" in ln})
+    assert len(paths) == 1, paths
+    hip = ctypes.CDLL(paths[0])
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    return hip
+
+
+def hip_malloc(nbytes):
+    """A device allocation of exactly `nbytes` (torch's caching allocator
+    would hand out a slice of a larger segment); free with hip_free."""
+    import ctypes
+    torch_cuda().cuda.synchronize()
+    p = ctypes.c_void_p()
+    assert hip_runtime().hipMalloc(ctypes.byref(p), nbytes) == 0
+    return p.value
+
+
+def hip_free(ptr):
+    hip_runtime().hipFree(ptr)

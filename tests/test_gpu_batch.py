@@ -33,15 +33,13 @@ def workload():
     return shapes, list(ins), list(fs)
 
 
-@pytest.mark.parametrize("flags", [0, C.CONV2D_BATCH_PER_GROUP])
-def test_batch_uneven_workload_matches_oracle_and_plain(workload, flags):
+def test_batch_uneven_workload_matches_oracle_and_plain(workload):
     """64 problems, square outputs log-uniform in [256, 2048], filters from
     {3, 5, 9, 17}: every output within tolerance of the FP64 oracle and bitwise
-    equal to a plain conv2d_run of the same problem (multi-filter kernel, and
-    one kernel per filter size)."""
+    equal to a plain conv2d_run of the same problem."""
     torch = torch_cuda()
     shapes, ins, fs = workload
-    batch = C.Batch(shapes, flags=flags)
+    batch = C.Batch(shapes)
     say(f"batch groups {batch.info}")
     outs = [torch.full((H, W), float("nan"), device="cuda") for (H, W, _, _) in shapes]
     batch(ins, fs, outs)
@@ -114,8 +112,8 @@ def test_batch_edge_cases():
 
 
 def test_batch_many_filter_sizes():
-    """Eleven filter sizes (more than one multi-filter kernel holds), uneven
-    images, integer data: bitwise equal to the oracle on every replay."""
+    """Eleven filter sizes (eleven persistent kernels as graph branches),
+    uneven images, integer data: bitwise equal to the oracle on every replay."""
     torch = torch_cuda()
     filters = [(1, 1), (3, 3), (5, 5), (7, 7), (9, 9), (11, 11), (2, 6), (6, 2), (17, 17), (31, 31), (4, 4)]
     shapes = [(40 + 13 * k, 70 - 5 * k, fh, fw) for k, (fh, fw) in enumerate(filters)]

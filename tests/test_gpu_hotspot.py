@@ -9,7 +9,7 @@ import pytest
 
 import datagen
 import oracle
-from tests.gpu_util import say, to_dev, torch_cuda
+from tests.gpu_util import hip_free, hip_malloc, say, to_dev, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def test_reference_matches_oracle(rows, cols, steps):
     torch = torch_cuda()
     temp = datagen.uniform_pm1(61, rows * cols).reshape(rows, cols)
     power = datagen.uniform_pm1(62, rows * cols).reshape(rows, cols)
-    out = C.hotspot_reference(to_dev(temp), to_dev(power), steps, STRESS)
+    out = C.reference_hotspot(to_dev(temp), to_dev(power), steps, STRESS)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     ref = oracle.hotspot_f64(temp, power, steps, *STRESS)
@@ -72,7 +72,7 @@ def test_stratified_configs_bitwise():
     temp = datagen.uniform_pm1(63, rows * cols).reshape(rows, cols)
     power = datagen.uniform_pm1(64, rows * cols).reshape(rows, cols)
     td, pd = to_dev(temp), to_dev(power)
-    ref = C.hotspot_reference(td, pd, steps, STRESS)
+    ref = C.reference_hotspot(td, pd, steps, STRESS)
     torch.cuda.synchronize()
     ref = ref.cpu().numpy()
     assert np.max(np.abs(ref - oracle.hotspot_f64(temp, power, steps, *STRESS))) <= bound(temp, power, steps, STRESS)
@@ -132,19 +132,20 @@ def test_errors_are_reported_not_faulted():
         a = torch.zeros((64, 64), device="cuda")
         b = torch.zeros((64, 64), device="cuda")
         o = torch.zeros((64, 64), device="cuda")
-        small = torch.zeros((10, 10), device="cuda")
+        small = hip_malloc(400)                   # a real 400-byte allocation
         with pytest.raises(C.Conv2dError):        # two launches, no work buffer
             C.hotspot_run(h, a.data_ptr(), b.data_ptr(), o.data_ptr(), 0, 3, k, st)
         with pytest.raises(C.Conv2dError):        # output overlaps the input
             C.hotspot_run(h, a.data_ptr(), b.data_ptr(), a.data_ptr(), 0, 1, k, st)
         with pytest.raises(C.Conv2dError):        # buffer too small for the grid
-            C.hotspot_run(h, small.data_ptr(), b.data_ptr(), o.data_ptr(), 0, 1, k, st)
+            C.hotspot_run(h, small, b.data_ptr(), o.data_ptr(), 0, 1, k, st)
         with pytest.raises(C.Conv2dError):
             C.hotspot_run(h, a.data_ptr(), b.data_ptr(), o.data_ptr(), 0, -1, k, st)
         with pytest.raises(C.Conv2dError):        # work buffer is the output
             C.hotspot_run(h, a.data_ptr(), b.data_ptr(), o.data_ptr(), o.data_ptr(), 3, k, st)
         C.hotspot_run(h, a.data_ptr(), b.data_ptr(), o.data_ptr(), 0, 2, k, st)   # one launch: no work buffer
         torch.cuda.synchronize()
+        hip_free(small)
     finally:
         C.hotspot_destroy(h)
     with pytest.raises(C.Conv2dError):

@@ -15,8 +15,11 @@ pytestmark = pytest.mark.gpu
 C = pytest.importorskip("paper_2407_11488_amd")
 
 
-def small_trace(n=48, rate=20000.0, seed=11, lo=32, hi=384):
+def small_trace(n=48, rate=20000.0, seed=11, lo=32, hi=384, burst=0):
+    """n requests, Poisson arrivals; the first `burst` arrive together at t = 0
+    (they are admitted together and so share a batch)."""
     t = datagen.poisson_arrivals(rate, n / rate * 3, seed=seed)[:n]
+    t[:burst] = 0.0
     sides = datagen.log_uniform_sides(seed + 1, len(t), lo, hi)
     fs = datagen.filter_choices(seed + 1, len(t))
     shapes = [(int(s), int(s) + (k % 3), int(f), int(f)) for k, (s, f) in enumerate(zip(sides, fs))]
@@ -60,7 +63,7 @@ def _plain(shape, seed_in, seed_f):
 
 @pytest.mark.parametrize("serial", [0, 1])
 def test_results_same_alone_and_in_the_mix(serial):
-    reqs, shapes = small_trace()
+    reqs, shapes = small_trace(burst=12)
     o = C.conv2d_serve_defaults()
     o.serial_plain = serial
     o.streams = 3

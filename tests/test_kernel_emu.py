@@ -155,54 +155,6 @@ def test_emulated_batch_kernel_exact(fh, fw, tmp_path):
                 assert np.array_equal(got.astype(np.float64), ref), (cfg, grid, k)
 
 
-# Groups of the multi-filter kernel (k, FH, FW, BX, BY, TX, TY, LDS, UNROLL),
-# 64 threads each, covering LDS and global-memory groups, x and y tiling,
-# non-square filters and the rolled and unrolled row loops.
-MULTI_GROUPS = [(0, 5, 5, 16, 4, 2, 2, 1, 1), (1, 3, 3, 64, 1, 4, 4, 0, 1), (2, 4, 2, 8, 8, 1, 3, 1, 2),
-                (3, 1, 1, 32, 2, 8, 1, 0, 0)]
-
-
-def build_multi(groups, nt):
-    glist = "".join("G(%s)" % ",".join(str(v) for v in g) for g in groups)
-    defs = {"CONV_BATCH": "2", "CONV_NT": str(nt), "CONV_GROUPS": glist, "CONV_NAME": "conv2d_multi"}
-    src = open(KERNEL).read() + open(os.path.join(EMU, "emu_multi.cpp")).read() + \
-        open(os.path.join(EMU, "hip_emu.h")).read()
-    key = hashlib.sha1((src + repr(sorted(defs.items()))).encode()).hexdigest()[:16]
-    os.makedirs(BIN_DIR, exist_ok=True)
-    exe = os.path.join(BIN_DIR, f"emum_{key}")
-    if not os.path.exists(exe):
-        cmd = [CXX, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-               "-fno-omit-frame-pointer", *[f"-D{k}={v}" for k, v in defs.items()],
-               os.path.join(EMU, "emu_multi.cpp"), "-o", exe + ".tmp", "-lpthread"]
-        subprocess.run(cmd, check=True, capture_output=True)
-        os.replace(exe + ".tmp", exe)
-    return exe
-
-
-def test_emulated_multi_filter_kernel_exact(tmp_path):
-    """The multi-filter persistent kernel over uneven images of four filter
-    sizes: every output of every image written once and exact, over two
-    launches, for several grid sizes; the tile counters return to 0."""
-    sizes = [(37, 45, 0), (5, 130, 1), (64, 64, 2), (1, 1, 3), (19, 7, 0), (33, 9, 2), (8, 200, 1), (3, 3, 3)]
-    probs = []
-    for k, (H, W, g) in enumerate(sizes):
-        fh, fw = MULTI_GROUPS[g][1], MULTI_GROUPS[g][2]
-        inp, f = datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=300 + k, seed_f=400 + k)
-        inp.astype(np.float32).tofile(tmp_path / f"in{k}.f32")
-        f.astype(np.float32).tofile(tmp_path / f"f{k}.f32")
-        probs.append((H, W, g, oracle.conv2d_f64(inp, f)[0]))
-    exe = build_multi(MULTI_GROUPS, 64)
-    args = [str(v) for H, W, g, _ in probs for v in (H, W, g)]
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    for grid in (1, 7, 16):
-        r = subprocess.run([exe, str(grid), str(tmp_path), str(len(probs)), *args], capture_output=True,
-                           text=True, env=env, timeout=300)
-        assert r.returncode == 0, r.stderr[-3000:]
-        for k, (H, W, g, ref) in enumerate(probs):
-            got = np.fromfile(tmp_path / f"out{k}.f32", np.float32).reshape(H, W)
-            assert np.array_equal(got.astype(np.float64), ref), (grid, k)
-
-
 # Hotspot configurations (block_x, block_y, tile_x, tile_y, temporal,
 # unroll_t, sh_power): one cell per thread, x and y tiling, temporal factors
 # from 1 to 8 with full and partial last launches, both power modes.
