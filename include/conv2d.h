@@ -263,7 +263,7 @@ typedef struct conv2d_tune_opts {
     const char *results_path;  /* per-configuration results, JSON lines, resumable (NULL: none) */
     int warmup;                /* untimed launches per configuration (default 2) */
     int reps;                  /* timed launches per configuration (default 20) */
-    int retime_reps;           /* re-timing launches for the top 5 (default 50) */
+    int retime_reps;           /* sustained launches re-timing the ten fastest (default 200) */
     int flush_mall;            /* 1: overwrite a 512 MiB buffer before each timed launch */
     int threads;               /* host compile threads (0: all cores, at most 16) */
     int unroll;                /* unroll value for every point (default 1) */
@@ -281,18 +281,18 @@ typedef struct conv2d_tune_opts {
 
 typedef struct conv2d_tune_result {
     conv2d_config best;        /* the winner */
-    double best_ms;            /* its median time after re-timing */
+    double best_ms;            /* its sustained time per launch (re-timing) */
     double default_ms;         /* median time of the default configuration (0 if not timed) */
     double median_ms;          /* time of the median-throughput configuration */
     double best_gflops, median_gflops, default_gflops;
-    double impact;             /* best / median throughput (the paper's tuning impact) */
+    double impact;             /* best / median throughput of the sweep (the paper's tuning impact) */
     int n_space;               /* points in the restricted product */
     int n_illegal;             /* rejected by the shape-dependent restrictions (LDS) */
     int n_compile_fail, n_launch_fail, n_verify_fail;
     int n_timed;               /* configurations timed successfully */
     int n_resumed;             /* results reused from results_path */
     int default_rank;          /* 1-based rank of the default among timed configs (0: n/a) */
-    conv2d_config top[5];      /* fastest five, fastest first */
+    conv2d_config top[5];      /* fastest five after re-timing, fastest first */
     double top_ms[5];
     double compile_s, measure_s; /* wall time of the compile and measure phases */
     int evaluations;           /* configurations measured in this call (failures included) */
@@ -303,10 +303,13 @@ void conv2d_tune_defaults(conv2d_tune_opts *opts);
 
 /* Compiles every legal point (in parallel on host threads), then for each:
  * launches it once and checks its output bitwise against the reference kernel,
- * times it with HIP events (median of `reps`), and records it. The top five
- * are re-timed, the winner chosen (lowest time; ties within tie_rel go to the
- * smallest configuration tuple) and stored in the winners cache. Inputs are
- * the seeded uniform recipe (input seed 1, filter seed 2), on device. */
+ * times it with HIP events (median of `reps` launches, each after a cache
+ * flush), and records it. The ten fastest are re-timed with `retime_reps`
+ * sustained launches (back to back, cycling through copies of the data that
+ * together exceed the last-level cache); the winner is the lowest sustained
+ * time, ties within tie_rel going to the smallest configuration tuple, and is
+ * stored in the winners cache. Inputs are the seeded uniform recipe (input
+ * seed 1, filter seed 2), on device. */
 int conv2d_tune(conv2d_shape s, const conv2d_tune_opts *opts, conv2d_tune_result *res);
 
 /* Times one configuration the way the tuner does: seeded inputs on the

@@ -64,7 +64,8 @@ typedef struct hotspot_plan_s *hotspot_plan_t;
 /* (32, 8, 1, 1, 1, 1, 1): one cell per thread, one step per launch. */
 void hotspot_default_config(hotspot_config *cfg);
 
-/* LDS bytes of a configuration (two region buffers). */
+/* LDS bytes of a configuration: two buffers of the region with a one-cell
+ * ring, 2 * (rows + 2) * ((cols + 2) | 1) floats. */
 int hotspot_lds_bytes(const hotspot_config *cfg);
 
 /* CONV2D_OK if cfg is a legal point: every value on its axis, at most 1024
@@ -115,7 +116,7 @@ typedef struct hotspot_tune_opts {
     const char *results_path;  /* per-configuration results (JSON lines; resumable), or NULL */
     int warmup;                /* untimed runs per point (default 2) */
     int reps;                  /* timed runs per point, median taken (default 20) */
-    int retime_reps;           /* timed runs of the five fastest, again (default 50) */
+    int retime_reps;           /* sustained runs re-timing the ten fastest (default 200) */
     int flush_mall;            /* 1: read 512 MiB between timed runs (default 1) */
     int threads;               /* compile threads (0: hardware threads, at most 16) */
     int max_configs;           /* first N legal points only (0: all) */
@@ -139,9 +140,11 @@ void hotspot_tune_defaults(hotspot_tune_opts *o);
 
 /* Sweeps the restricted space for grid s and `steps` steps per run (each
  * point compiled, verified bitwise against hotspot_reference on seeded data,
- * timed as a whole hotspot_run), picks the winner (lowest median; ties within
- * tie_rel to the smallest tuple) and appends it to the winners cache.
- * Throughput counts 14 floating-point operations per cell and step. */
+ * timed as a whole hotspot_run after a cache flush, median of `reps`),
+ * re-times the ten fastest with sustained runs (as conv2d_tune), picks the
+ * winner (lowest sustained time; ties within tie_rel to the smallest tuple)
+ * and appends it to the winners cache. Throughput counts 14 floating-point
+ * operations per cell and step. */
 int hotspot_tune(hotspot_shape s, int steps, const hotspot_tune_opts *opts, hotspot_tune_result *res);
 
 #ifdef __cplusplus

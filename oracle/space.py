@@ -39,8 +39,8 @@ def restricted():
 # unroll, power staging), restricted to 64..1024 threads, a region of
 # (block_y*tile_y) x (block_x*tile_x) cells larger than twice the temporal
 # factor along both axes (a non-empty output tile), and two LDS buffers of
-# rows x (cols + 1) floats within 160 KiB (never binding here: at most 16,384
-# cells per region, 131,200 bytes).
+# (rows + 2) x ((cols + 2) | 1) floats (the region and a one-cell ring, odd
+# pitch) within 160 KiB (never binding here: at most 147,888 bytes).
 HOTSPOT_AXES = (
     ("block_x", (16, 32, 64, 128, 256)),
     ("block_y", (1, 2, 4, 8, 16)),
@@ -62,7 +62,7 @@ def hotspot_restricted():
             continue
         if rows <= 2 * tt or cols <= 2 * tt:
             continue
-        if 2 * rows * (cols + 1) * 4 > HOTSPOT_LDS_LIMIT:
+        if 2 * (rows + 2) * ((cols + 2) | 1) * 4 > HOTSPOT_LDS_LIMIT:
             continue
         out.append(c)
     return out

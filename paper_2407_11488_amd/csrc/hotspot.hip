@@ -24,8 +24,9 @@
 // Design (MI355X): a workgroup owns a region of (BY*TY) x (BX*TX) cells, its
 // output tile plus a halo of TT cells on every side; neighbouring regions
 // overlap by 2*TT. Each thread keeps its TY x TX cells in VGPRs through all
-// steps. Per step it publishes them to one of two LDS buffers, waits once, and
-// reads from LDS only the ring of neighbours that belong to other threads.
+// steps. Per step it publishes them to one of two LDS buffers (each with a
+// zero ring around the region), waits once, and reads from LDS only the ring
+// of neighbours that belong to other threads.
 // After s steps the cells at distance >= s from the region's edge are exact;
 // after the launch's steps (<= TT) the inner tile is stored. The grid edge is
 // handled by coordinates, never by reading outside the grid.
@@ -42,7 +43,13 @@
 #define RW (HS_BX * HS_TX)   // region columns
 #define OH (RH - 2 * HS_TT)  // output tile rows
 #define OW (RW - 2 * HS_TT)  // output tile columns
-#define LDS_PITCH (RW + 1)   // odd pitch: a wave's column reads spread over the banks
+// LDS buffer: the region plus a one-cell ring (cell (R, C) at LIDX(R, C)),
+// so that every neighbour read of a region cell stays inside the buffer and
+// needs no test; ring cells are zero and feed only cells that are not exact
+// anyway. Odd pitch: a wave's column reads spread over the banks.
+#define LDS_PITCH ((RW + 2) | 1)
+#define LDS_CELLS ((RH + 2) * LDS_PITCH)
+#define LIDX(R, C) (((R) + 1) * LDS_PITCH + (C) + 1)
 
 #if OH < 1 || OW < 1
 #error "the region must be larger than twice the temporal tiling factor"
@@ -76,7 +83,7 @@ static __device__ __forceinline__ float cell_step(float t, float north, float so
 // grid-edge rule, and the per-cell coordinate tests disappear.
 template <bool EDGE>
 static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const float (&pw)[HS_TY][HS_TX],
-                                                 float (*buf)[RH * LDS_PITCH], const float* __restrict__ power,
+                                                 float (*buf)[LDS_CELLS], const float* __restrict__ power,
                                                  int rows, int cols, int steps, int R0, int C0, int gr0, int gc0,
                                                  float cc, float gx, float gy, float gz, float t_amb)
 {
@@ -93,7 +100,7 @@ static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const
         for (int a = 0; a < HS_TY; ++a)
 #pragma unroll
             for (int b = 0; b < HS_TX; ++b)
-                cur[(R0 + a) * LDS_PITCH + C0 + b] = v[a][b];
+                cur[LIDX(R0 + a, C0 + b)] = v[a][b];
         __syncthreads();
 
         float nv[HS_TY][HS_TX];
@@ -105,21 +112,21 @@ static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const
                 const int C = C0 + b, gc = gc0 + b;
                 const float t = v[a][b];
                 // Neighbours: the cell itself at the grid's edge; a register
-                // inside the thread's block; else LDS (the region's own edge
-                // reads the cell itself: such cells are never exact anyway).
+                // inside the thread's block; else LDS (at the region's own
+                // edge, the zero ring: such cells are never exact anyway).
                 float north, south, west, east;
                 if (EDGE && gr == 0) north = t;
                 else if (a > 0) north = v[a - 1][b];
-                else north = R > 0 ? cur[(R - 1) * LDS_PITCH + C] : t;
+                else north = cur[LIDX(R - 1, C)];
                 if (EDGE && gr == rows - 1) south = t;
                 else if (a < HS_TY - 1) south = v[a + 1][b];
-                else south = R < RH - 1 ? cur[(R + 1) * LDS_PITCH + C] : t;
+                else south = cur[LIDX(R + 1, C)];
                 if (EDGE && gc == 0) west = t;
                 else if (b > 0) west = v[a][b - 1];
-                else west = C > 0 ? cur[R * LDS_PITCH + C - 1] : t;
+                else west = cur[LIDX(R, C - 1)];
                 if (EDGE && gc == cols - 1) east = t;
                 else if (b < HS_TX - 1) east = v[a][b + 1];
-                else east = C < RW - 1 ? cur[R * LDS_PITCH + C + 1] : t;
+                else east = cur[LIDX(R, C + 1)];
 #if HS_SH_POWER
                 const float p = pw[a][b];
 #else
@@ -140,7 +147,7 @@ extern "C" __global__ void __launch_bounds__(HS_NT)
 HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* __restrict__ tout, int rows,
         int cols, int steps, int tiles_x, int n_tiles, float cc, float gx, float gy, float gz, float t_amb)
 {
-    __shared__ float buf[2][RH * LDS_PITCH];
+    __shared__ float buf[2][LDS_CELLS];
     const int tile = xcd_remap((int)blockIdx.x, n_tiles);
     const int tile_y = tile / tiles_x;
     const int tile_x = tile - tile_y * tiles_x;
@@ -163,6 +170,17 @@ HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* _
             v[a][b] = tin[row + c];
             pw[a][b] = HS_SH_POWER ? power[row + c] : 0.0f;
         }
+    }
+
+    // Zero the rings of both buffers (no thread's cells live there). The
+    // first step's barrier orders these writes before any read.
+    for (int k = (int)threadIdx.x; k < 2 * (RW + 2) + 2 * RH; k += HS_NT) {
+        int r, c;
+        if (k < RW + 2) { r = -1; c = k - 1; }
+        else if (k < 2 * (RW + 2)) { r = RH; c = k - (RW + 2) - 1; }
+        else { r = (k - 2 * (RW + 2)) >> 1; c = (k & 1) ? RW : -1; }
+        buf[0][LIDX(r, c)] = 0.0f;
+        buf[1][LIDX(r, c)] = 0.0f;
     }
 
     // Workgroup-uniform: does the region touch (or cross) the grid's edge?

@@ -42,6 +42,12 @@ public:
     // Verify and time one prepared config (reps timed launches); best_so_far
     // (0: none) lets a far slower point stop early.
     virtual int measure(const Cfg& c, int warmup, int reps, double best_so_far, RecordT<Cfg>* r) = 0;
+    // Sustained timing for later measure() calls: the reps launches run back
+    // to back, as an application runs them, cycling through copies of the
+    // data larger together than the last-level cache so that every launch
+    // starts cold, and the mean is taken. Off: each launch is timed alone
+    // after a cache flush.
+    virtual void set_sustained(bool on) { (void)on; }
 };
 
 // Prepares and measures every configuration of `todo`, storing each record in
@@ -74,39 +80,48 @@ int measure_all(const std::vector<Cfg>& todo, MeasurerT<Cfg>* m, int warmup, int
     return CONV2D_OK;
 }
 
-// Sorts `eligible` (verified records) by time, ties by less(); re-times the
-// n_top fastest with retime_reps repetitions (0: no re-timing) and sorts
-// again; the winner is the smallest configuration under less() whose time is
-// within tie_rel of the fastest.
+// Sorts `eligible` (verified records of the sweep) by time, ties by less();
+// re-times the n_top fastest with retime_reps sustained launches (0: keeps
+// the sweep's times) into *top, sorted by the new time; the winner is the
+// smallest configuration under less() among those within tie_rel of the
+// fastest of *top. Only re-timed points compete: the sweep times a launch
+// alone after a cache flush, which favours configurations that do well in
+// bursts, while applications run launches back to back.
 template <class Cfg, class Less>
 int retime_and_pick(std::vector<RecordT<Cfg>>* eligible, MeasurerT<Cfg>* m, int warmup, int retime_reps,
-                    int n_top, double tie_rel, Less less, RecordT<Cfg>* win)
+                    int n_top, double tie_rel, Less less, std::vector<RecordT<Cfg>>* top, RecordT<Cfg>* win)
 {
     if (eligible->empty()) return fail(CONV2D_EVERIFY, "no configuration compiled, ran and verified");
     auto by_time = [&](const RecordT<Cfg>& a, const RecordT<Cfg>& b) {
         return a.ms != b.ms ? a.ms < b.ms : less(a.c, b.c);
     };
     std::sort(eligible->begin(), eligible->end(), by_time);
-    n_top = std::min<int>(n_top, (int)eligible->size());
-    if (retime_reps > 0 && n_top > 0) {
-        std::vector<Cfg> top;
-        for (int k = 0; k < n_top; ++k) top.push_back((*eligible)[k].c);
+    n_top = std::max(1, std::min<int>(n_top, (int)eligible->size()));
+    top->assign(eligible->begin(), eligible->begin() + n_top);
+    if (retime_reps > 0) {
+        std::vector<Cfg> cfgs;
+        for (const auto& r : *top) cfgs.push_back(r.c);
         std::vector<int> st;
         double sec = 0;
-        int rc = m->prepare(top, &st, &sec);
+        int rc = m->prepare(cfgs, &st, &sec);
         if (rc) return rc;
-        for (int k = 0; k < n_top; ++k) {
+        m->set_sustained(true);
+        std::vector<RecordT<Cfg>> timed;
+        for (int k = 0; k < n_top && rc == CONV2D_OK; ++k) {
             if (st[k] != kOk) continue;
             RecordT<Cfg> r;
-            rc = m->measure(top[k], warmup, retime_reps, 0, &r);
-            if (rc) return rc;
-            if (r.status == kOk) (*eligible)[k] = r;
+            rc = m->measure(cfgs[k], warmup, retime_reps, 0, &r);
+            if (rc == CONV2D_OK && r.status == kOk) timed.push_back(r);
         }
-        std::sort(eligible->begin(), eligible->end(), by_time);
+        m->set_sustained(false);
+        if (rc) return rc;
+        if (timed.empty()) return fail(CONV2D_EVERIFY, "re-timing: no configuration ran and verified");
+        *top = timed;
     }
-    const double fastest = (*eligible)[0].ms;
-    *win = (*eligible)[0];
-    for (const auto& r : *eligible)
+    std::sort(top->begin(), top->end(), by_time);
+    const double fastest = (*top)[0].ms;
+    *win = (*top)[0];
+    for (const auto& r : *top)
         if (r.ms <= fastest * (1.0 + tie_rel) && less(r.c, win->c)) *win = r;
     return CONV2D_OK;
 }

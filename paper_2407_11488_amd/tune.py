@@ -2,7 +2,7 @@
 
 One shape:
     python -m paper_2407_11488_amd.tune --shape 4096 4096 17 17 [--results PATH]
-        [--winners PATH] [--reps 20] [--retime-reps 50] [--no-flush] [--unroll 1]
+        [--winners PATH] [--reps 20] [--retime-reps 200] [--no-flush] [--unroll 1]
         [--no-refine-unroll] [--max-configs N] [--json OUT]
 
 Filter-size sweep (each shape tuned, then compared with a reference shape's
@@ -118,7 +118,7 @@ def main(argv=None) -> int:
     ap.add_argument("--winners", default=DEFAULT_WINNERS)
     ap.add_argument("--results", default=None)
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--retime-reps", type=int, default=50)
+    ap.add_argument("--retime-reps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-flush", action="store_true")
     ap.add_argument("--unroll", type=int, default=1)

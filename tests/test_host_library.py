@@ -161,7 +161,7 @@ def test_synthetic_tuner_matches_statistics_oracle(tmp_path):
     calls = []
     r2 = C.conv2d_tune_synthetic(s, lambda c: calls.append(c) or table[c], o)
     assert r2.n_resumed == 1202 and r2.best.tuple() == r.best.tuple()
-    assert len(calls) <= 10          # only the re-timing of the top five
+    assert len(calls) <= 20          # only the re-timing of the ten fastest (prepare + measure)
 
 
 def test_synthetic_tuner_records_failures(tmp_path):
@@ -273,9 +273,9 @@ def test_hotspot_config_check_errors():
                 (32, 8, 1, 1, 1, 1, 2)]:
         assert C.hotspot_config_check(s, bad) == C.CONV2D_EINVAL, bad
         assert C.conv2d_last_error()
-    # 16384 cells in two buffers need 131,200 bytes of LDS: legal at 160 KiB,
-    # rejected under a 64 KiB limit
-    assert C.hotspot_lds_bytes((256, 4, 4, 4, 1, 1, 1)) == 131200
+    # a 16 x 1024 region in two ringed buffers needs 147,888 bytes of LDS:
+    # legal at 160 KiB, rejected under a 64 KiB limit
+    assert C.hotspot_lds_bytes((256, 4, 4, 4, 1, 1, 1)) == 147888
     assert C.hotspot_config_check(s, (256, 4, 4, 4, 1, 1, 1)) == 0
     assert C.hotspot_config_check(s, (256, 4, 4, 4, 1, 1, 1), 65536) == C.CONV2D_EINVAL
     assert C.hotspot_config_check(C.hotspot_shape(0, 4), (32, 8, 1, 1, 1, 1, 1)) == C.CONV2D_EINVAL
