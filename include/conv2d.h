@@ -168,7 +168,8 @@ int conv2d_fill_uniform(float *d_out, size_t n, uint64_t seed, uint64_t start, v
  * grouped by filter size; each group runs the tuned configuration of its filter
  * size (winners cache entry for 4096x4096 with that filter, else the most
  * recent entry with that filter, else the default; the filter is always read
- * through its pointer) as one persistent kernel over the group's tiles. The
+ * through its pointer) as one kernel over the group's tiles (a workgroup per
+ * tile, the tiles of each image in row order, XCD-contiguous runs). The
  * groups are parallel branches of one graph captured at plan time. Results
  * are bitwise identical to conv2d_run / conv2d_reference on the same data.
  * A batch plan must not run on two streams at once (its descriptor table is
@@ -191,7 +192,8 @@ int conv2d_batch_run(conv2d_batch_t batch, const float *const *d_in, const float
 
 /* Groups of a batch: their count, the total tile count, and for the first
  * `cap` groups the filter size (filt[2g], filt[2g+1]), configuration and
- * persistent grid size. Any output pointer may be NULL. */
+ * grid size (one workgroup per tile, at least 8). Any output pointer may be
+ * NULL. */
 int conv2d_batch_info(conv2d_batch_t batch, int *n_groups, int *total_tiles, int *filt,
                       conv2d_config *cfgs, int *grids, int cap);
 
@@ -212,7 +214,7 @@ int conv2d_compile_batch(conv2d_shape s, const conv2d_config *cfg, char *path_ou
  * conv2d_fill_uniform), standing in for an image that arrives in HBM. When
  * one of `streams` streams is free, every admitted request not yet launched
  * (up to max_batch) is launched as one batch: one fill launch, then one
- * persistent batched kernel per filter size present (as in conv2d_batch_run).
+ * batched kernel per filter size present (as in conv2d_batch_run).
  * Batches on different streams overlap on the device. A request's latency
  * runs from its arrival time to the host observing its batch's completion
  * event; outputs stay on the device. serial_plain = 1 runs the same trace one

@@ -7,7 +7,7 @@
 // in for an image that arrives in HBM). Whenever one of K streams is free, all
 // admitted requests not yet launched (up to max_batch) go out as one batch:
 // one fill launch for every image and filter of the batch, then one
-// persistent batched kernel per filter size present. Batches on different
+// batched kernel per filter size present. Batches on different
 // streams overlap on the device; completion is observed with events, and each
 // request's latency runs from its arrival to the host seeing its batch done.
 //
@@ -97,7 +97,6 @@ struct Req {
 struct FilterKernel {
     conv2d_config cfg{};
     Module mod;
-    int grid_cap = 0;     // resident workgroups on the whole GPU
 };
 
 struct Slot {
@@ -162,12 +161,6 @@ public:
                 FilterKernel fk;
                 rc = batch_module_for_filter(dev_, s.filt_h, s.filt_w, &fk.cfg, &fk.mod);
                 if (rc) return rc;
-                int per_cu = 0;
-                if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fk.mod.fn,
-                                                                       fk.cfg.block_x * fk.cfg.block_y, 0) != hipSuccess ||
-                    per_cu < 1)
-                    per_cu = 1;
-                fk.grid_cap = per_cu * dev_.cus;
                 kernels_.emplace(key, fk);
             }
             if (!o_.serial_plain) {
@@ -328,7 +321,7 @@ private:
         int rc = launch_fill_uniform_batch(d_fill, (int)(2 * nb), max_n, s.st);
         if (rc) return rc;
         for (const G& g : groups) {
-            const int grid = std::max(8, std::min(g.tiles, g.fk->grid_cap));
+            const int grid = std::max(8, g.tiles);   // one workgroup per tile, as the batched path
             rc = launch_batch_kernel(g.fk->mod, g.fk->cfg, grid, d_desc + g.d0, d_owner + g.o0, g.tiles, s.st);
             if (rc) return rc;
         }
