@@ -25,7 +25,7 @@
 //   CONV_VOUT          output vector width 1/2/4 (row pitch and base aligned)
 //   CONV_NAME          kernel symbol (one per configuration, so that profiles
 //                      tell configurations apart); default conv2d_direct
-//   CONV_BATCH         1: build the batched kernel (many images of
+//   CONV_BATCH         1: build the persistent batched kernel (many images of
 //                      one filter size, described in device memory) instead
 //
 // Design (MI355X):
@@ -291,7 +291,7 @@ static __device__ __forceinline__ const ConvDesc* tile_desc(const ConvDesc* __re
     return descs + __builtin_amdgcn_readfirstlane((int)owner[t]);
 }
 
-// Many images with the same filter size: a grid (at least 8
+// Many images with the same filter size: a persistent grid (at least 8
 // workgroups) walks the group's tile list. The tiles of XCD x (= workgroup id
 // mod 8) form one contiguous range, shared out by stride among that XCD's
 // workgroups; owner[t] names the problem of tile t.
