@@ -166,7 +166,8 @@ int conv2d_fill_uniform(float *d_out, size_t n, uint64_t seed, uint64_t start, v
  * Many convolutions of uneven sizes in one hipGraph launch (not part of the
  * paper: the batching extension of its convolution kernel). Problems are
  * grouped by filter size; each group runs the tuned configuration of its filter
- * size (winners cache entry for 4096x4096 with that filter, else the most
+ * size (the batched path's own entry (0, 0, fh, fw) from conv2d_batch_tune,
+ * else the winners cache entry for 4096x4096 with that filter, else the most
  * recent entry with that filter, else the default; the filter is always read
  * through its pointer) as one kernel over the group's tiles (a workgroup per
  * tile, the tiles of each image in row order, XCD-contiguous runs). The
@@ -198,6 +199,41 @@ int conv2d_batch_info(conv2d_batch_t batch, int *n_groups, int *total_tiles, int
                       conv2d_config *cfgs, int *grids, int cap);
 
 void conv2d_batch_destroy(conv2d_batch_t batch);
+
+/* Tunes the batched path on a batch: for each filter size present, the
+ * `candidates` fastest points of the tuner's 4096x4096 sweep for that filter
+ * (results_<arch>_4096x4096_<fh>x<fw>.jsonl in results_dir; filter through
+ * its pointer) and the current choice are each run as the batch's
+ * kernel for that filter over the batch's problems of that size (seeded data
+ * on the device), verified bitwise against the reference kernel and timed
+ * with `reps` sustained launches; the fastest (ties within tie_rel go to the
+ * smallest tuple) is appended to the winners cache under the shape
+ * (0, 0, fh, fw), which conv2d_batch_plan and conv2d_serve look up before the
+ * 4096x4096 winner. Not part of the paper (its tuner tunes one kernel on one
+ * problem); this is the batched path's own tuning. */
+#define CONV2D_BATCH_TUNE_MAX 16
+typedef struct conv2d_batch_tune_opts {
+    const char *winners_path;  /* winners cache read and appended (NULL: $CONV2D_WINNERS or the default) */
+    const char *results_dir;   /* sweep results (NULL: the tuned/ directory beside the library) */
+    int candidates;            /* sweep points tried per filter size (default 12) */
+    int warmup, reps;          /* per candidate (default 3 and 50) */
+    double tie_rel;            /* default 0.005 */
+    int verbose;
+} conv2d_batch_tune_opts;
+
+typedef struct conv2d_batch_tune_result {
+    int n_groups;                                  /* filter sizes (the first CONV2D_BATCH_TUNE_MAX reported) */
+    int filt[2 * CONV2D_BATCH_TUNE_MAX];           /* fh, fw of group g at 2g, 2g+1 */
+    conv2d_config before[CONV2D_BATCH_TUNE_MAX];   /* the choice before tuning */
+    conv2d_config after[CONV2D_BATCH_TUNE_MAX];    /* the winner */
+    double before_ms[CONV2D_BATCH_TUNE_MAX];       /* the group's kernel, sustained, ms per launch */
+    double after_ms[CONV2D_BATCH_TUNE_MAX];
+    int n_tried[CONV2D_BATCH_TUNE_MAX];            /* candidates that compiled, ran and verified */
+} conv2d_batch_tune_result;
+
+void conv2d_batch_tune_defaults(conv2d_batch_tune_opts *opts);
+int conv2d_batch_tune(int n, const conv2d_shape *shapes, const conv2d_batch_tune_opts *opts,
+                      conv2d_batch_tune_result *res);
 
 /* Compiles the batched kernel of a configuration (filter read through its
  * pointer, scalar loads and stores) for gfx950 with hiprtc, no GPU needed.

@@ -312,6 +312,46 @@ def conv2d_batch_info(batch: int, cap: int = 64) -> dict:
     return {"n_groups": ng.value, "total_tiles": tiles.value, "groups": groups}
 
 
+BATCH_TUNE_MAX = 16
+
+
+class BatchTuneOpts(ctypes.Structure):
+    _fields_ = [("winners_path", c_char_p), ("results_dir", c_char_p), ("candidates", c_int), ("warmup", c_int), ("reps", c_int),
+                ("tie_rel", c_double), ("verbose", c_int)]
+
+
+class BatchTuneResult(ctypes.Structure):
+    _fields_ = [("n_groups", c_int), ("filt", c_int * (2 * BATCH_TUNE_MAX)), ("before", Config * BATCH_TUNE_MAX),
+                ("after", Config * BATCH_TUNE_MAX), ("before_ms", c_double * BATCH_TUNE_MAX),
+                ("after_ms", c_double * BATCH_TUNE_MAX), ("n_tried", c_int * BATCH_TUNE_MAX)]
+
+    def groups(self):
+        return [{"filter": (self.filt[2 * g], self.filt[2 * g + 1]), "before": list(self.before[g].tuple()),
+                 "before_ms": round(self.before_ms[g], 5), "after": list(self.after[g].tuple()),
+                 "after_ms": round(self.after_ms[g], 5), "tried": self.n_tried[g]}
+                for g in range(min(self.n_groups, BATCH_TUNE_MAX))]
+
+
+lib.conv2d_batch_tune_defaults.restype = None
+lib.conv2d_batch_tune_defaults.argtypes = [P(BatchTuneOpts)]
+lib.conv2d_batch_tune.restype = c_int
+lib.conv2d_batch_tune.argtypes = [c_int, P(Shape), P(BatchTuneOpts), P(BatchTuneResult)]
+
+
+def conv2d_batch_tune_defaults() -> BatchTuneOpts:
+    o = BatchTuneOpts()
+    lib.conv2d_batch_tune_defaults(ctypes.byref(o))
+    return o
+
+
+def conv2d_batch_tune(shapes, opts: BatchTuneOpts | None = None) -> BatchTuneResult:
+    arr = (Shape * len(shapes))(*[shape(*s) for s in shapes])
+    r = BatchTuneResult()
+    check(lib.conv2d_batch_tune(len(shapes), arr, None if opts is None else ctypes.byref(opts), ctypes.byref(r)),
+          "conv2d_batch_tune")
+    return r
+
+
 def conv2d_batch_destroy(batch: int) -> None:
     lib.conv2d_batch_destroy(batch)
 

@@ -9,11 +9,15 @@
 // changed since the last run).
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
 #include <mutex>
 
 #include "internal.h"
+#include "search.h"
 
 namespace conv2d {
 namespace {
@@ -125,22 +129,41 @@ static int capture(conv2d_batch_s* b)
 
 namespace conv2d {
 
-int batch_module_for_filter(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m)
+// Winners-cache shape of the batched path's own tuning of a filter size.
+static conv2d_shape batch_key(int fh, int fw) { return conv2d_shape{0, 0, fh, fw}; }
+
+static std::string winners_path_or_default(const char* given)
 {
+    if (given && *given) return given;
     std::string wp = env_str("CONV2D_WINNERS");
-    if (wp.empty()) wp = winners_default_path();
+    return wp.empty() ? winners_default_path() : wp;
+}
+
+// The configuration the batched path uses for a filter size (before
+// building: the build may still fall back to the rolled loop).
+static conv2d_config batch_config_for_filter(const DeviceInfo& dev, const std::string& wp, int fh, int fw)
+{
     const conv2d_shape tuned_shape{4096, 4096, fh, fw};
-    if (cache_lookup_filter(wp, dev.arch, fh, fw, tuned_shape, cfg) != CONV2D_OK) conv2d_default_config(cfg);
+    conv2d_config cfg{};
+    if (cache_lookup(wp, dev.arch, batch_key(fh, fw), &cfg, nullptr) != CONV2D_OK &&
+        cache_lookup_filter(wp, dev.arch, fh, fw, tuned_shape, &cfg) != CONV2D_OK)
+        conv2d_default_config(&cfg);
     clear_error();
-    cfg->filter_in_const = 0;  // each problem has its own filter
-    if (conv2d_config_check(tuned_shape, cfg, dev.lds_limit) != CONV2D_OK) {
-        conv2d_default_config(cfg);
-        cfg->filter_in_const = 0;
+    cfg.filter_in_const = 0;  // each problem has its own filter
+    if (conv2d_config_check(tuned_shape, &cfg, dev.lds_limit) != CONV2D_OK) {
+        conv2d_default_config(&cfg);
+        cfg.filter_in_const = 0;
         clear_error();
     }
+    return cfg;
+}
+
+int batch_module_for_filter(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m)
+{
+    *cfg = batch_config_for_filter(dev, winners_path_or_default(nullptr), fh, fw);
     // The batched kernel stores with scalar writes (any row alignment); with
     // a fully unrolled row loop that can spill, and the rolled loop is used.
-    return build_module(tuned_shape, cfg, 1, 1, dev.arch, true, true, m);
+    return build_module(conv2d_shape{4096, 4096, fh, fw}, cfg, 1, 1, dev.arch, true, true, m);
 }
 
 int launch_batch_kernel(const Module& m, const conv2d_config& cfg, int grid, const void* d_desc,
@@ -337,6 +360,274 @@ extern "C" int conv2d_compile_batch(conv2d_shape s, const conv2d_config* cfg, ch
     if (path_out && path_cap > 0) {
         std::strncpy(path_out, path.c_str(), (size_t)path_cap - 1);
         path_out[path_cap - 1] = '\0';
+    }
+    return CONV2D_OK;
+}
+
+// ---------------------------------------------------------------- batch tuning
+
+namespace conv2d {
+namespace {
+
+// The fastest `k` verified points of the 4096x4096 sweep of a filter size
+// (any kernel source), filter moved to its pointer, legal, without repeats.
+std::vector<conv2d_config> sweep_leaders(const DeviceInfo& dev, const std::string& dir, int fh, int fw, int k)
+{
+    char name[128];
+    std::snprintf(name, sizeof name, "/results_%s_4096x4096_%dx%d.jsonl", dev.arch.c_str(), fh, fw);
+    std::ifstream f(dir + name);
+    std::vector<std::pair<double, conv2d_config>> all;
+    std::string line;
+    while (std::getline(f, line)) {
+        JsonObj o;
+        if (!json_parse_line(line, &o) || o.str["arch"] != dev.arch || o.str["status"] != "ok") continue;
+        auto sh = o.arr.find("shape"), cf = o.arr.find("config");
+        if (sh == o.arr.end() || cf == o.arr.end() || sh->second.size() != 4 || cf->second.size() != 7) continue;
+        if ((int)sh->second[0] != 4096 || (int)sh->second[1] != 4096 || (int)sh->second[2] != fh ||
+            (int)sh->second[3] != fw)
+            continue;
+        const auto& v = cf->second;
+        all.push_back({o.num["ms"], conv2d_config{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], 0, (int)v[6]}});
+    }
+    std::stable_sort(all.begin(), all.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    std::vector<conv2d_config> out;
+    const conv2d_shape s{4096, 4096, fh, fw};
+    for (const auto& e : all) {
+        if ((int)out.size() >= k) break;
+        bool seen = false;
+        for (const auto& c : out) seen = seen || config_equal(c, e.second);
+        if (seen || conv2d_config_check(s, &e.second, dev.lds_limit) != CONV2D_OK) continue;
+        out.push_back(e.second);
+    }
+    clear_error();
+    return out;
+}
+
+// One filter size's problems of a batch on the device: seeded inputs and
+// filters, reference outputs, outputs, and the descriptor and owner tables
+// of the batched kernel for a configuration.
+struct GroupBench {
+    std::vector<conv2d_shape> shapes;
+    std::vector<float*> in, f, out, ref;
+    ConvDesc* d_desc = nullptr;
+    unsigned short* d_owner = nullptr;
+    unsigned* d_count = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int tiles = 0;
+
+    ~GroupBench()
+    {
+        if (st) hipStreamSynchronize(st);
+        for (auto* v : {&in, &f, &out, &ref})
+            for (float* p : *v)
+                if (p) hipFree(p);
+        if (d_desc) hipFree(d_desc);
+        if (d_owner) hipFree(d_owner);
+        if (d_count) hipFree(d_count);
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        if (st) hipStreamDestroy(st);
+    }
+
+    int init()
+    {
+        CONV2D_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        CONV2D_HIP(hipEventCreate(&e0));
+        CONV2D_HIP(hipEventCreate(&e1));
+        if (hipMalloc(&d_desc, sizeof(ConvDesc) * shapes.size()) != hipSuccess ||
+            hipMalloc(&d_count, sizeof(unsigned)) != hipSuccess)
+            return fail(CONV2D_ENOMEM, "batch tune: device allocation");
+        for (size_t k = 0; k < shapes.size(); ++k) {
+            const conv2d_shape& s = shapes[k];
+            const size_t n_in = (size_t)(s.out_h + s.filt_h - 1) * (s.out_w + s.filt_w - 1);
+            const size_t n_out = (size_t)s.out_h * s.out_w;
+            float *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
+            if (hipMalloc(&a, n_in * 4) != hipSuccess || hipMalloc(&b, 4ull * s.filt_h * s.filt_w) != hipSuccess ||
+                hipMalloc(&c, n_out * 4) != hipSuccess || hipMalloc(&d, n_out * 4) != hipSuccess) {
+                for (float* p : {a, b, c, d})
+                    if (p) hipFree(p);
+                return fail(CONV2D_ENOMEM, "batch tune: device allocation");
+            }
+            in.push_back(a);
+            f.push_back(b);
+            out.push_back(c);
+            ref.push_back(d);
+            int rc = launch_fill_uniform(a, n_in, 1000 + k, 0, st);
+            if (!rc) rc = launch_fill_uniform(b, (size_t)s.filt_h * s.filt_w, 2000 + k, 0, st);
+            if (!rc) rc = launch_reference(s, a, b, d, st);
+            if (rc) return rc;
+        }
+        CONV2D_HIP(hipStreamSynchronize(st));
+        return CONV2D_OK;
+    }
+
+    // Descriptor and owner tables for a configuration's tiles.
+    int layout(const conv2d_config& c)
+    {
+        std::vector<ConvDesc> descs(shapes.size());
+        std::vector<unsigned short> owner;
+        long long total = 0;
+        for (size_t k = 0; k < shapes.size(); ++k) {
+            const conv2d_shape& s = shapes[k];
+            const Geometry geo = geometry(s.out_h, s.out_w, c);
+            descs[k] = ConvDesc{in[k], f[k], out[k], s.out_h, s.out_w, geo.tiles_x, (int)total,
+                                (unsigned)(4ull * (s.out_h + s.filt_h - 1) * (s.out_w + s.filt_w - 1)), geo.n_tiles};
+            owner.insert(owner.end(), (size_t)geo.n_tiles, (unsigned short)k);
+            total += geo.n_tiles;
+        }
+        if (total > INT_MAX) return fail(CONV2D_EINVAL, "batch tune: too many tiles");
+        tiles = (int)total;
+        if (d_owner) hipFree(d_owner);
+        d_owner = nullptr;
+        if (hipMalloc(&d_owner, sizeof(unsigned short) * owner.size()) != hipSuccess)
+            return fail(CONV2D_ENOMEM, "batch tune: device allocation");
+        CONV2D_HIP(hipMemcpy(d_desc, descs.data(), sizeof(ConvDesc) * descs.size(), hipMemcpyHostToDevice));
+        CONV2D_HIP(hipMemcpy(d_owner, owner.data(), sizeof(unsigned short) * owner.size(), hipMemcpyHostToDevice));
+        return CONV2D_OK;
+    }
+
+    int launch(const Module& m, const conv2d_config& c)
+    {
+        return launch_batch_kernel(m, c, std::max(8, tiles), d_desc, d_owner, tiles, st);
+    }
+
+    // One launch on NaN-filled outputs, then a bitwise comparison with the
+    // reference; *ok tells whether every output matched.
+    int verify(const Module& m, const conv2d_config& c, bool* ok)
+    {
+        for (size_t k = 0; k < shapes.size(); ++k) {
+            int rc = launch_fill_value(out[k], (size_t)shapes[k].out_h * shapes[k].out_w, __builtin_nanf(""), st);
+            if (rc) return rc;
+        }
+        int rc = launch(m, c);
+        if (rc) return rc;
+        CONV2D_HIP(hipMemsetAsync(d_count, 0, sizeof(unsigned), st));
+        for (size_t k = 0; k < shapes.size() && !rc; ++k)
+            rc = launch_count_mismatch(out[k], ref[k], (size_t)shapes[k].out_h * shapes[k].out_w, d_count, st);
+        if (rc) return rc;
+        unsigned bad = 0;
+        CONV2D_HIP(hipMemcpyAsync(&bad, d_count, sizeof bad, hipMemcpyDeviceToHost, st));
+        CONV2D_HIP(hipStreamSynchronize(st));
+        *ok = bad == 0;
+        return CONV2D_OK;
+    }
+
+    int time_sustained(const Module& m, const conv2d_config& c, int warmup, int reps, double* ms)
+    {
+        for (int k = 0; k < warmup; ++k) {
+            int rc = launch(m, c);
+            if (rc) return rc;
+        }
+        CONV2D_HIP(hipEventRecord(e0, st));
+        for (int k = 0; k < reps; ++k) {
+            int rc = launch(m, c);
+            if (rc) return rc;
+        }
+        CONV2D_HIP(hipEventRecord(e1, st));
+        CONV2D_HIP(hipEventSynchronize(e1));
+        float t = 0;
+        CONV2D_HIP(hipEventElapsedTime(&t, e0, e1));
+        *ms = t / reps;
+        return CONV2D_OK;
+    }
+};
+
+}  // namespace
+}  // namespace conv2d
+
+extern "C" void conv2d_batch_tune_defaults(conv2d_batch_tune_opts* o)
+{
+    if (!o) return;
+    *o = conv2d_batch_tune_opts{};
+    o->candidates = 12;
+    o->warmup = 3;
+    o->reps = 50;
+    o->tie_rel = 0.005;
+}
+
+extern "C" int conv2d_batch_tune(int n, const conv2d_shape* shapes, const conv2d_batch_tune_opts* opts,
+                                 conv2d_batch_tune_result* res)
+{
+    clear_error();
+    if (!res) return fail(CONV2D_EINVAL, "res is NULL");
+    *res = conv2d_batch_tune_result{};
+    if (n < 1 || !shapes) return fail(CONV2D_EINVAL, "a batch needs n >= 1 shapes");
+    for (int i = 0; i < n; ++i) {
+        int rc = shape_check(shapes[i]);
+        if (rc) return fail(rc, "problem " + std::to_string(i) + ": " + last_error_cstr());
+    }
+    conv2d_batch_tune_opts o;
+    conv2d_batch_tune_defaults(&o);
+    if (opts) o = *opts;
+    o.candidates = std::max(0, o.candidates);
+    o.warmup = std::max(0, o.warmup);
+    o.reps = std::max(1, o.reps);
+    o.tie_rel = std::max(0.0, o.tie_rel);
+    DeviceInfo dev;
+    int rc = current_device_info(&dev);
+    if (rc) return rc;
+    const std::string wp = winners_path_or_default(o.winners_path);
+    const std::string rdir = (o.results_dir && *o.results_dir) ? std::string(o.results_dir) : library_dir() + "/tuned";
+
+    std::map<std::pair<int, int>, std::vector<conv2d_shape>> by_filter;
+    for (int i = 0; i < n; ++i) by_filter[{shapes[i].filt_h, shapes[i].filt_w}].push_back(shapes[i]);
+    res->n_groups = (int)by_filter.size();
+    int g = 0;
+    for (const auto& kv : by_filter) {
+        const int fh = kv.first.first, fw = kv.first.second;
+        GroupBench gb;
+        gb.shapes = kv.second;
+        rc = gb.init();
+        if (rc) return rc;
+        const conv2d_config current = batch_config_for_filter(dev, wp, fh, fw);
+        std::vector<conv2d_config> cands{current};
+        for (const auto& c : sweep_leaders(dev, rdir, fh, fw, o.candidates)) {
+            bool seen = false;
+            for (const auto& e : cands) seen = seen || config_equal(e, c);
+            if (!seen) cands.push_back(c);
+        }
+        std::vector<RecordT<conv2d_config>> timed;
+        double current_ms = 0;
+        for (size_t k = 0; k < cands.size(); ++k) {
+            conv2d_config c = cands[k];
+            Module m;
+            if (build_module(conv2d_shape{4096, 4096, fh, fw}, &c, 1, 1, dev.arch, true, true, &m) != CONV2D_OK) {
+                clear_error();
+                continue;
+            }
+            bool ok = false;
+            rc = gb.layout(c);
+            if (!rc) rc = gb.verify(m, c, &ok);
+            double ms = 0;
+            if (!rc && ok) rc = gb.time_sustained(m, c, o.warmup, o.reps, &ms);
+            unload_module(&m);
+            if (rc) return rc;
+            if (!ok) continue;
+            if (k == 0) current_ms = ms;
+            timed.push_back(RecordT<conv2d_config>{c, kOk, ms, ms, ms, o.reps});
+            if (o.verbose)
+                std::fprintf(stderr, "[batch tune] %dx%d %s: %.4f ms\n", fh, fw, config_str(c).c_str(), ms);
+        }
+        if (timed.empty()) return fail(CONV2D_EVERIFY, "batch tune: no configuration ran and verified");
+        std::sort(timed.begin(), timed.end(), [](const auto& a, const auto& b) {
+            return a.ms != b.ms ? a.ms < b.ms : config_less(a.c, b.c);
+        });
+        RecordT<conv2d_config> win = timed[0];
+        for (const auto& r : timed)
+            if (r.ms <= timed[0].ms * (1.0 + o.tie_rel) && config_less(r.c, win.c)) win = r;
+        rc = cache_store(wp, dev.arch, batch_key(fh, fw), win.c, win.ms);
+        if (rc) return rc;
+        if (g < CONV2D_BATCH_TUNE_MAX) {
+            res->filt[2 * g] = fh;
+            res->filt[2 * g + 1] = fw;
+            res->before[g] = current;
+            res->after[g] = win.c;
+            res->before_ms[g] = current_ms;
+            res->after_ms[g] = win.ms;
+            res->n_tried[g] = (int)timed.size();
+        }
+        ++g;
     }
     return CONV2D_OK;
 }

@@ -10,6 +10,11 @@ winner applied unchanged):
     python -m paper_2407_11488_amd.tune --size 4096 --filters 3 7 15 31 --ref-filter 17 \
         --results-dir DIR
 
+The batched path's configurations on the 64-problem uneven workload (each
+filter size's fastest 4096x4096 sweep points, timed as that size's batched
+kernel over the batch's problems; stored as the (0, 0, fh, fw) winners):
+    python -m paper_2407_11488_amd.tune --batch [--candidates 12]
+
 Hotspot stencil (the second tunable kernel), one grid and step count:
     python -m paper_2407_11488_amd.tune --hotspot 4096 4096 --steps 60 [--results PATH]
 
@@ -131,9 +136,21 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--json", default=None)
     ap.add_argument("--hotspot", type=int, nargs=2, metavar=("ROWS", "COLS"))
+    ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--candidates", type=int, default=12)
     ap.add_argument("--steps", type=int, default=60)
     a = ap.parse_args(argv)
 
+    if a.batch:
+        import datagen
+        o = B.conv2d_batch_tune_defaults()
+        o.winners_path = a.winners.encode()
+        o.results_dir = (a.results_dir or os.path.dirname(DEFAULT_WINNERS)).encode()
+        o.candidates, o.verbose = a.candidates, 1
+        r = B.conv2d_batch_tune(datagen.batch_shapes(64), o)
+        emit({"workload": "batched, 64 problems (sides log-uniform [256, 2048], filters {3,5,9,17})",
+              "groups": r.groups()}, a.json)
+        return 0
     if a.hotspot:
         rows, cols = a.hotspot
         results = a.results or os.path.join(os.path.dirname(DEFAULT_WINNERS),

@@ -1,6 +1,8 @@
 """GPU parity of the batched path (conv2d_batch_plan / conv2d_batch_run),
 through the C ABI: the 64-problem uneven workload against the FP64 oracle and
 bitwise against the plain path, graph replays, pointer changes, and errors."""
+import os
+
 import numpy as np
 import pytest
 
@@ -150,3 +152,48 @@ def test_batch_errors():
             C.conv2d_batch_run(b, [inp.data_ptr()], [f.data_ptr()], [inp.data_ptr()])
     finally:
         C.conv2d_batch_destroy(b)
+
+
+def test_batch_tune_stores_and_is_used(tmp_path, monkeypatch):
+    """conv2d_batch_tune on a small two-filter batch: every filter size gets a
+    verified winner no slower than the current choice, stored as the
+    (0, 0, fh, fw) entry; a batch planned afterwards uses it, and its outputs
+    still match the oracle."""
+    import shutil
+    torch = torch_cuda()
+    wp = tmp_path / "winners.jsonl"
+    here = os.path.join(os.path.dirname(C.LIB_PATH), "tuned")
+    shutil.copy(os.path.join(here, "winners.jsonl"), wp)
+    for f in (3, 9):
+        src = os.path.join(here, f"results_gfx950_4096x4096_{f}x{f}.jsonl")
+        if os.path.exists(src):
+            shutil.copy(src, tmp_path / os.path.basename(src))
+    shapes = [(300, 300, 9, 9), (200, 260, 9, 9), (150, 150, 3, 3), (520, 400, 3, 3)]
+    o = C.conv2d_batch_tune_defaults()
+    o.winners_path = str(wp).encode()
+    o.results_dir = str(tmp_path).encode()
+    o.candidates, o.reps = 4, 5
+    r = C.conv2d_batch_tune(shapes, o)
+    groups = r.groups()
+    say(f"batch tune: {groups}")
+    assert r.n_groups == 2
+    for g in groups:
+        assert g["tried"] >= 1 and g["after_ms"] > 0
+        assert g["after_ms"] <= g["before_ms"] * (1 + o.tie_rel) + 1e-9
+        got = C.conv2d_cache_lookup(str(wp), None, C.shape(0, 0, *g["filter"]))[0].tuple()
+        assert got == tuple(g["after"])
+    monkeypatch.setenv("CONV2D_WINNERS", str(wp))
+    b = C.Batch(shapes)
+    used = {tuple(x["filter"]): tuple(x["config"]) for x in b.info["groups"]}
+    for g in groups:
+        want = tuple(g["after"])
+        assert used[tuple(g["filter"])][:6] == want[:6]      # the build may roll the row loop
+    ins, fs = zip(*[_device_problem(torch, s, 90 + p) for p, s in enumerate(shapes)])
+    outs = b(list(ins), list(fs))
+    torch.cuda.synchronize()
+    for p, (H, W, fh, fw) in enumerate(shapes):
+        inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=datagen.SEED_BATCH_INPUT_BASE + 90 + p,
+                                      seed_f=datagen.SEED_BATCH_FILTER_BASE + 90 + p)
+        ref, s = oracle.conv2d_f64(inp, f)
+        assert oracle.normalized_error(outs[p].cpu().numpy(), ref, s) <= TOL
+    b.close()
