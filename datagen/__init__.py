@@ -50,6 +50,7 @@ SEED_INPUT = 1
 SEED_FILTER = 2
 SEED_BATCH_SHAPES = 3
 SEED_ARRIVALS = 4
+SEED_SERVING_SAMPLE = 5
 SEED_BATCH_INPUT_BASE = 1000
 SEED_BATCH_FILTER_BASE = 2000
 
@@ -160,6 +161,15 @@ def serving_requests(rate_hz: float, duration_s: float, lo: int = 128, hi: int =
     sides = log_uniform_sides(seed + 7919, len(t), lo, hi)
     fs = filter_choices(seed + 7919, len(t))
     return t, [(int(s), int(s), int(f), int(f)) for s, f in zip(sides, fs)]
+
+
+def serving_sample(n: int = 160, lo: int = 128, hi: int = 4096, seed: int = SEED_SERVING_SAMPLE):
+    """``n`` request shapes drawn like the served workload's (square sides
+    log-uniform in [lo, hi], filters from {3, 5, 9, 17}) from a seed of their
+    own, so that tuning for serving does not see the served trace."""
+    sides = log_uniform_sides(seed, n, lo, hi)
+    fs = filter_choices(seed, n)
+    return [(int(s), int(s), int(f), int(f)) for s, f in zip(sides, fs)]
 
 
 # ---------------------------------------------------------------- hotspot workload

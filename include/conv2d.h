@@ -164,13 +164,16 @@ int conv2d_fill_uniform(float *d_out, size_t n, uint64_t seed, uint64_t start, v
 /* ---------------------------------------------------------------- batched path
  *
  * Many convolutions of uneven sizes in one hipGraph launch (not part of the
- * paper: the batching extension of its convolution kernel). Problems are
- * grouped by filter size; each group runs the tuned configuration of its filter
- * size (the batched path's own entry (0, 0, fh, fw) from conv2d_batch_tune,
- * else the winners cache entry for 4096x4096 with that filter, else the most
- * recent entry with that filter, else the default; the filter is always read
- * through its pointer) as one kernel over the group's tiles (a workgroup per
- * tile, the tiles of each image in row order, XCD-contiguous runs). The
+ * paper: the batching extension of its convolution kernel). Each problem
+ * gets a tuned configuration for its filter size: the batched path's own
+ * whole-batch entry (0, 0, fh, fw) from conv2d_batch_tune, else its size
+ * bucket's entry (0, b, fh, fw) (with CONV2D_BATCH_BY_SIZE the other way
+ * round), else the winners cache entry for 4096x4096 with that filter, else
+ * the most recent entry with that filter, else the default; the filter is
+ * always read through its pointer. The problems sharing a filter size and
+ * configuration form a group, run as one kernel over the group's tiles (a
+ * workgroup per tile, the tiles of each image in row order, XCD-contiguous
+ * runs). The
  * groups are parallel branches of one graph captured at plan time. Results
  * are bitwise identical to conv2d_run / conv2d_reference on the same data.
  * A batch plan must not run on two streams at once (its descriptor table is
@@ -178,7 +181,8 @@ int conv2d_fill_uniform(float *d_out, size_t n, uint64_t seed, uint64_t start, v
 
 enum {
     CONV2D_BATCH_NO_GRAPH = 1,     /* launch the group kernels directly instead of a graph */
-    CONV2D_BATCH_NO_PTR_CHECK = 2  /* skip the per-problem allocation checks */
+    CONV2D_BATCH_NO_PTR_CHECK = 2, /* skip the per-problem allocation checks */
+    CONV2D_BATCH_BY_SIZE = 4       /* each problem takes its size bucket's configuration */
 };
 
 /* Plans n problems (n <= 65535); shapes[i] as for conv2d_plan. */
@@ -200,30 +204,41 @@ int conv2d_batch_info(conv2d_batch_t batch, int *n_groups, int *total_tiles, int
 
 void conv2d_batch_destroy(conv2d_batch_t batch);
 
-/* Tunes the batched path on a batch: for each filter size present, the
- * `candidates` fastest points of the tuner's 4096x4096 sweep for that filter
- * (results_<arch>_4096x4096_<fh>x<fw>.jsonl in results_dir; filter through
- * its pointer) and the current choice are each run as the batch's
- * kernel for that filter over the batch's problems of that size (seeded data
- * on the device), verified bitwise against the reference kernel and timed
- * with `reps` sustained launches; the fastest (ties within tie_rel go to the
- * smallest tuple) is appended to the winners cache under the shape
- * (0, 0, fh, fw), which conv2d_batch_plan and conv2d_serve look up before the
- * 4096x4096 winner. Not part of the paper (its tuner tunes one kernel on one
- * problem); this is the batched path's own tuning. */
-#define CONV2D_BATCH_TUNE_MAX 16
+/* Size buckets of the batched path's tuning cache, by the larger output
+ * side: 1 (up to 384), 2 (385-768), 3 (769-1536), 4 (1537-3072), 5 (larger). */
+#define CONV2D_SIZE_BUCKETS 5
+
+/* Tunes the batched path on a batch: the problems are grouped by filter size
+ * (and, with `buckets`, by size bucket too); for each group, its current
+ * configuration, the `candidates` fastest points of the tuner's 4096x4096
+ * sweep for that filter (results_<arch>_4096x4096_<fh>x<fw>.jsonl in
+ * results_dir) and the fastest point of every workgroup tile area of that
+ * sweep (filter always through its pointer) are each run as the batched
+ * kernel over the group's problems (seeded data on the device), verified
+ * bitwise against the reference kernel and timed with `reps` sustained
+ * launches. The fastest (ties within tie_rel go to the smallest tuple) is
+ * appended to the winners cache under the shape (0, 0, fh, fw), or
+ * (0, b, fh, fw) for size bucket b (conv2d_batch_plan prefers the first,
+ * conv2d_serve and CONV2D_BATCH_BY_SIZE plans the second). Candidates are
+ * compiled on up
+ * to 16 host threads first. Not part of the paper (its tuner tunes one kernel
+ * on one problem); this is the batched path's own tuning. */
+#define CONV2D_BATCH_TUNE_MAX 32
 typedef struct conv2d_batch_tune_opts {
     const char *winners_path;  /* winners cache read and appended (NULL: $CONV2D_WINNERS or the default) */
     const char *results_dir;   /* sweep results (NULL: the tuned/ directory beside the library) */
-    int candidates;            /* sweep points tried per filter size (default 12) */
+    int candidates;            /* fastest sweep points tried per group (default 12) */
+    int buckets;               /* 1: one configuration per filter size and size bucket (default 0) */
     int warmup, reps;          /* per candidate (default 3 and 50) */
     double tie_rel;            /* default 0.005 */
     int verbose;
 } conv2d_batch_tune_opts;
 
 typedef struct conv2d_batch_tune_result {
-    int n_groups;                                  /* filter sizes (the first CONV2D_BATCH_TUNE_MAX reported) */
+    int n_groups;                                  /* groups (the first CONV2D_BATCH_TUNE_MAX reported) */
     int filt[2 * CONV2D_BATCH_TUNE_MAX];           /* fh, fw of group g at 2g, 2g+1 */
+    int bucket[CONV2D_BATCH_TUNE_MAX];             /* size bucket of group g (0: all sizes) */
+    int n_problems[CONV2D_BATCH_TUNE_MAX];         /* problems of the batch in group g */
     conv2d_config before[CONV2D_BATCH_TUNE_MAX];   /* the choice before tuning */
     conv2d_config after[CONV2D_BATCH_TUNE_MAX];    /* the winner */
     double before_ms[CONV2D_BATCH_TUNE_MAX];       /* the group's kernel, sustained, ms per launch */
@@ -250,7 +265,8 @@ int conv2d_compile_batch(conv2d_shape s, const conv2d_config *cfg, char *path_ou
  * conv2d_fill_uniform), standing in for an image that arrives in HBM. When
  * one of `streams` streams is free, every admitted request not yet launched
  * (up to max_batch) is launched as one batch: one fill launch, then one
- * batched kernel per filter size present (as in conv2d_batch_run).
+ * batched kernel per filter size and configuration present, each request
+ * taking its size bucket's configuration (as a CONV2D_BATCH_BY_SIZE batch).
  * Batches on different streams overlap on the device. A request's latency
  * runs from its arrival time to the host observing its batch's completion
  * event; outputs stay on the device. serial_plain = 1 runs the same trace one

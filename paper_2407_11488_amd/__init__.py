@@ -19,7 +19,7 @@ from ._binding import (CONV2D_EBUSY, CONV2D_ECOMPILE, CONV2D_EHIP, CONV2D_EINVAL
                        conv2d_lds_bytes, conv2d_plan, conv2d_plan_config, conv2d_reference, conv2d_run,
                        conv2d_space, conv2d_tune, conv2d_tune_defaults, conv2d_tune_synthetic,
                        conv2d_version, lib, shape)
-from ._binding import (CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK, conv2d_batch_destroy,  # noqa: F401
+from ._binding import (CONV2D_BATCH_BY_SIZE, CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK, conv2d_batch_destroy,  # noqa: F401
                        conv2d_batch_info, conv2d_batch_plan, conv2d_batch_run, conv2d_batch_tune,
                        conv2d_batch_tune_defaults, conv2d_compile_batch)
 from ._binding import (REQUEST_DTYPE, ServeOpts, ServeReport, conv2d_serve, conv2d_serve_defaults,  # noqa: F401

@@ -272,7 +272,7 @@ def conv2d_benchmark(s: Shape, cfg, warmup: int = 2, reps: int = 20, flush_mall:
     return med.value, mn.value
 
 
-CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK = 1, 2
+CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK, CONV2D_BATCH_BY_SIZE = 1, 2, 4
 
 for _name, (_res, _args) in {
     "conv2d_batch_plan": (c_int, [P(c_void_p), c_int, P(Shape), c_int]),
@@ -312,21 +312,24 @@ def conv2d_batch_info(batch: int, cap: int = 64) -> dict:
     return {"n_groups": ng.value, "total_tiles": tiles.value, "groups": groups}
 
 
-BATCH_TUNE_MAX = 16
+BATCH_TUNE_MAX = 32
+SIZE_BUCKETS = 5
 
 
 class BatchTuneOpts(ctypes.Structure):
-    _fields_ = [("winners_path", c_char_p), ("results_dir", c_char_p), ("candidates", c_int), ("warmup", c_int), ("reps", c_int),
-                ("tie_rel", c_double), ("verbose", c_int)]
+    _fields_ = [("winners_path", c_char_p), ("results_dir", c_char_p), ("candidates", c_int), ("buckets", c_int),
+                ("warmup", c_int), ("reps", c_int), ("tie_rel", c_double), ("verbose", c_int)]
 
 
 class BatchTuneResult(ctypes.Structure):
-    _fields_ = [("n_groups", c_int), ("filt", c_int * (2 * BATCH_TUNE_MAX)), ("before", Config * BATCH_TUNE_MAX),
+    _fields_ = [("n_groups", c_int), ("filt", c_int * (2 * BATCH_TUNE_MAX)), ("bucket", c_int * BATCH_TUNE_MAX),
+                ("n_problems", c_int * BATCH_TUNE_MAX), ("before", Config * BATCH_TUNE_MAX),
                 ("after", Config * BATCH_TUNE_MAX), ("before_ms", c_double * BATCH_TUNE_MAX),
                 ("after_ms", c_double * BATCH_TUNE_MAX), ("n_tried", c_int * BATCH_TUNE_MAX)]
 
     def groups(self):
-        return [{"filter": (self.filt[2 * g], self.filt[2 * g + 1]), "before": list(self.before[g].tuple()),
+        return [{"filter": (self.filt[2 * g], self.filt[2 * g + 1]), "bucket": self.bucket[g],
+                 "problems": self.n_problems[g], "before": list(self.before[g].tuple()),
                  "before_ms": round(self.before_ms[g], 5), "after": list(self.after[g].tuple()),
                  "after_ms": round(self.after_ms[g], 5), "tried": self.n_tried[g]}
                 for g in range(min(self.n_groups, BATCH_TUNE_MAX))]

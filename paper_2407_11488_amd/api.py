@@ -2,6 +2,8 @@
 and the current stream; all computation is in the HIP library)."""
 from __future__ import annotations
 
+import ctypes
+
 from . import _binding as B
 
 
@@ -108,6 +110,27 @@ class Batch:
         B.conv2d_batch_run(self.handle, [t.data_ptr() for t in inputs], [t.data_ptr() for t in filters],
                            [t.data_ptr() for t in outputs], _stream(stream))
         return outputs
+
+    def bind(self, inputs, filters, outputs):
+        """Checks the tensors once and returns a callable run(stream=None)
+        that enqueues the batch on them with no per-call Python checks (the
+        library still compares the pointers with the last upload). The
+        tensors must stay alive while the callable is used."""
+        if len(inputs) != len(self.shapes) or len(filters) != len(self.shapes) or len(outputs) != len(self.shapes):
+            raise ValueError("one input, filter and output per problem")
+        for k, (H, W, fh, fw) in enumerate(self.shapes):
+            _check_tensor(inputs[k], f"inputs[{k}]", (H + fh - 1, W + fw - 1))
+            _check_tensor(filters[k], f"filters[{k}]", (fh, fw))
+            _check_tensor(outputs[k], f"outputs[{k}]", (H, W))
+        n = len(self.shapes)
+        keep = (list(inputs), list(filters), list(outputs))
+        arrays = [(ctypes.c_void_p * n)(*[t.data_ptr() for t in ts]) for ts in keep]
+        handle, run = self.handle, B.lib.conv2d_batch_run
+
+        def bound(stream=None):
+            B.check(run(handle, *arrays, _stream(stream)), "conv2d_batch_run")
+            return keep[2]
+        return bound
 
     def close(self):
         if self.handle:

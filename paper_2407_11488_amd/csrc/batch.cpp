@@ -8,6 +8,7 @@
 // hipGraphLaunch (after a small descriptor upload when the caller's pointers
 // changed since the last run).
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdio>
 #include <cstring>
@@ -15,6 +16,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
+#include <tuple>
 
 #include "internal.h"
 #include "search.h"
@@ -129,8 +132,9 @@ static int capture(conv2d_batch_s* b)
 
 namespace conv2d {
 
-// Winners-cache shape of the batched path's own tuning of a filter size.
-static conv2d_shape batch_key(int fh, int fw) { return conv2d_shape{0, 0, fh, fw}; }
+// Winners-cache shape of the batched path's own tuning of a filter size:
+// (0, 0, fh, fw) for problems of any size, (0, b, fh, fw) for size bucket b.
+static conv2d_shape batch_key(int fh, int fw, int bucket) { return conv2d_shape{0, bucket, fh, fw}; }
 
 static std::string winners_path_or_default(const char* given)
 {
@@ -139,15 +143,28 @@ static std::string winners_path_or_default(const char* given)
     return wp.empty() ? winners_default_path() : wp;
 }
 
-// The configuration the batched path uses for a filter size (before
-// building: the build may still fall back to the rolled loop).
-static conv2d_config batch_config_for_filter(const DeviceInfo& dev, const std::string& wp, int fh, int fw)
+int size_bucket(int out_h, int out_w)
+{
+    const int side = std::max(out_h, out_w);
+    int b = 1;
+    for (int bound = 384; b < CONV2D_SIZE_BUCKETS && side > bound; bound *= 2) ++b;
+    return b;
+}
+
+// The configuration the batched path uses for a filter size: with a size
+// bucket (> 0), the bucket's entry, else the filter's whole-batch entry;
+// without (bucket 0), the whole-batch entry, else the entry of the bucket
+// `fallback_bucket`; then the 4096x4096 winner, else the default. The filter
+// is read through its pointer.
+static conv2d_config lookup_batch_config(const DeviceInfo& dev, const std::string& wp, int fh, int fw, int bucket,
+                                         int fallback_bucket = 0)
 {
     const conv2d_shape tuned_shape{4096, 4096, fh, fw};
     conv2d_config cfg{};
-    if (cache_lookup(wp, dev.arch, batch_key(fh, fw), &cfg, nullptr) != CONV2D_OK &&
-        cache_lookup_filter(wp, dev.arch, fh, fw, tuned_shape, &cfg) != CONV2D_OK)
-        conv2d_default_config(&cfg);
+    auto entry = [&](int b) { return cache_lookup(wp, dev.arch, batch_key(fh, fw, b), &cfg, nullptr) == CONV2D_OK; };
+    bool found = bucket > 0 ? entry(bucket) || entry(0) : entry(0) || (fallback_bucket > 0 && entry(fallback_bucket));
+    if (!found) found = cache_lookup_filter(wp, dev.arch, fh, fw, tuned_shape, &cfg) == CONV2D_OK;
+    if (!found) conv2d_default_config(&cfg);
     clear_error();
     cfg.filter_in_const = 0;  // each problem has its own filter
     if (conv2d_config_check(tuned_shape, &cfg, dev.lds_limit) != CONV2D_OK) {
@@ -158,9 +175,13 @@ static conv2d_config batch_config_for_filter(const DeviceInfo& dev, const std::s
     return cfg;
 }
 
-int batch_module_for_filter(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m)
+conv2d_config batch_config_for(const DeviceInfo& dev, int fh, int fw, int bucket, int fallback_bucket)
 {
-    *cfg = batch_config_for_filter(dev, winners_path_or_default(nullptr), fh, fw);
+    return lookup_batch_config(dev, winners_path_or_default(nullptr), fh, fw, bucket, fallback_bucket);
+}
+
+int batch_module(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m)
+{
     // The batched kernel stores with scalar writes (any row alignment); with
     // a fully unrolled row loop that can spill, and the rolled loop is used.
     return build_module(conv2d_shape{4096, 4096, fh, fw}, cfg, 1, 1, dev.arch, true, true, m);
@@ -201,22 +222,45 @@ extern "C" int conv2d_batch_plan(conv2d_batch_t* out, int n, const conv2d_shape*
     b->flags = flags;
     b->shapes.assign(shapes, shapes + n);
 
-    // Group by filter size, heaviest filters first.
-    std::map<std::pair<int, int>, std::vector<int>> by_filter;
-    for (int i = 0; i < n; ++i) by_filter[{shapes[i].filt_h, shapes[i].filt_w}].push_back(i);
-    std::vector<std::pair<int, int>> keys;
-    for (auto& kv : by_filter) keys.push_back(kv.first);
-    std::sort(keys.begin(), keys.end(), [](auto a, auto c) { return a.first * a.second > c.first * c.second; });
+    // Group by filter size and configuration, heaviest filters first. By
+    // default a filter size takes its whole-batch entry (one kernel for all
+    // its problems: a large mixed batch runs best so); CONV2D_BATCH_BY_SIZE
+    // gives each problem its size bucket's entry (the buckets of a filter that
+    // share a configuration share a kernel).
+    using Key = std::pair<std::pair<int, int>, std::string>;
+    std::map<std::tuple<int, int, int>, conv2d_config> chosen;
+    std::map<Key, std::vector<int>> by_kernel;
+    std::map<Key, conv2d_config> kernel_cfg;
+    for (int i = 0; i < n; ++i) {
+        const auto bk = std::make_tuple(shapes[i].filt_h, shapes[i].filt_w, size_bucket(shapes[i].out_h, shapes[i].out_w));
+        auto it = chosen.find(bk);
+        if (it == chosen.end()) {
+            const int bucket = std::get<2>(bk);
+            const conv2d_config c = (flags & CONV2D_BATCH_BY_SIZE)
+                                        ? batch_config_for(b->dev, shapes[i].filt_h, shapes[i].filt_w, bucket, 0)
+                                        : batch_config_for(b->dev, shapes[i].filt_h, shapes[i].filt_w, 0, bucket);
+            it = chosen.emplace(bk, c).first;
+        }
+        const Key key{{shapes[i].filt_h, shapes[i].filt_w}, config_str(it->second)};
+        by_kernel[key].push_back(i);
+        kernel_cfg[key] = it->second;
+    }
+    std::vector<Key> keys;
+    for (auto& kv : by_kernel) keys.push_back(kv.first);
+    std::stable_sort(keys.begin(), keys.end(), [](const Key& a, const Key& c) {
+        return a.first.first * a.first.second > c.first.first * c.first.second;
+    });
 
     std::vector<unsigned short> owner;
     std::vector<ConvDesc> proto;
     b->desc_slot.assign(n, -1);
     for (const auto& key : keys) {
         Group g;
-        g.fh = key.first;
-        g.fw = key.second;
-        g.problems = by_filter[key];
-        rc = batch_module_for_filter(b->dev, g.fh, g.fw, &g.cfg, &g.mod);
+        g.fh = key.first.first;
+        g.fw = key.first.second;
+        g.problems = by_kernel[key];
+        g.cfg = kernel_cfg[key];
+        rc = batch_module(b->dev, g.fh, g.fw, &g.cfg, &g.mod);
         if (rc) return rc;
         g.threads = g.cfg.block_x * g.cfg.block_y;
         g.desc_begin = proto.size();
@@ -369,9 +413,12 @@ extern "C" int conv2d_compile_batch(conv2d_shape s, const conv2d_config* cfg, ch
 namespace conv2d {
 namespace {
 
-// The fastest `k` verified points of the 4096x4096 sweep of a filter size
-// (any kernel source), filter moved to its pointer, legal, without repeats.
-std::vector<conv2d_config> sweep_leaders(const DeviceInfo& dev, const std::string& dir, int fh, int fw, int k)
+// Candidates from the 4096x4096 sweep of a filter size (any kernel source;
+// filter moved to its pointer; legal; no repeats): its `k` fastest verified
+// points, then the fastest point of every workgroup tile area (block_x *
+// tile_x * block_y * tile_y) not yet present, which gives small images
+// configurations with more, smaller tiles.
+std::vector<conv2d_config> sweep_candidates(const DeviceInfo& dev, const std::string& dir, int fh, int fw, int k)
 {
     char name[128];
     std::snprintf(name, sizeof name, "/results_%s_4096x4096_%dx%d.jsonl", dev.arch.c_str(), fh, fw);
@@ -392,18 +439,29 @@ std::vector<conv2d_config> sweep_leaders(const DeviceInfo& dev, const std::strin
     std::stable_sort(all.begin(), all.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
     std::vector<conv2d_config> out;
     const conv2d_shape s{4096, 4096, fh, fw};
+    auto add = [&](const conv2d_config& c) {
+        for (const auto& e : out)
+            if (config_equal(e, c)) return false;
+        if (conv2d_config_check(s, &c, dev.lds_limit) != CONV2D_OK) return false;
+        out.push_back(c);
+        return true;
+    };
     for (const auto& e : all) {
         if ((int)out.size() >= k) break;
-        bool seen = false;
-        for (const auto& c : out) seen = seen || config_equal(c, e.second);
-        if (seen || conv2d_config_check(s, &e.second, dev.lds_limit) != CONV2D_OK) continue;
-        out.push_back(e.second);
+        add(e.second);
+    }
+    std::map<long long, bool> areas;
+    for (const auto& c : out) areas[(long long)c.block_x * c.tile_x * c.block_y * c.tile_y] = true;
+    for (const auto& e : all) {
+        const conv2d_config& c = e.second;
+        const long long area = (long long)c.block_x * c.tile_x * c.block_y * c.tile_y;
+        if (!areas.count(area) && add(c)) areas[area] = true;
     }
     clear_error();
     return out;
 }
 
-// One filter size's problems of a batch on the device: seeded inputs and
+// One group's problems of a batch on the device: seeded inputs and
 // filters, reference outputs, outputs, and the descriptor and owner tables
 // of the batched kernel for a configuration.
 struct GroupBench {
@@ -570,29 +628,58 @@ extern "C" int conv2d_batch_tune(int n, const conv2d_shape* shapes, const conv2d
     const std::string wp = winners_path_or_default(o.winners_path);
     const std::string rdir = (o.results_dir && *o.results_dir) ? std::string(o.results_dir) : library_dir() + "/tuned";
 
-    std::map<std::pair<int, int>, std::vector<conv2d_shape>> by_filter;
-    for (int i = 0; i < n; ++i) by_filter[{shapes[i].filt_h, shapes[i].filt_w}].push_back(shapes[i]);
-    res->n_groups = (int)by_filter.size();
+    // Groups: (fh, fw, bucket), bucket 0 when not tuning by size.
+    std::map<std::tuple<int, int, int>, std::vector<conv2d_shape>> groups;
+    for (int i = 0; i < n; ++i) {
+        const int bk = o.buckets ? size_bucket(shapes[i].out_h, shapes[i].out_w) : 0;
+        groups[std::make_tuple(shapes[i].filt_h, shapes[i].filt_w, bk)].push_back(shapes[i]);
+    }
+    res->n_groups = (int)groups.size();
+
+    // Candidates of every group (the current choice first), compiled up front
+    // on a pool of host threads.
+    std::vector<std::vector<conv2d_config>> cands;
+    std::vector<std::pair<conv2d_shape, conv2d_config>> to_compile;
+    for (const auto& kv : groups) {
+        const int fh = std::get<0>(kv.first), fw = std::get<1>(kv.first), bk = std::get<2>(kv.first);
+        std::vector<conv2d_config> c{lookup_batch_config(dev, wp, fh, fw, bk)};
+        for (const auto& x : sweep_candidates(dev, rdir, fh, fw, o.candidates)) {
+            bool seen = false;
+            for (const auto& e : c) seen = seen || config_equal(e, x);
+            if (!seen) c.push_back(x);
+        }
+        for (const auto& x : c) to_compile.push_back({conv2d_shape{4096, 4096, fh, fw}, x});
+        cands.push_back(std::move(c));
+    }
+    {
+        const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+        std::atomic<size_t> next{0};
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthreads; ++t)
+            pool.emplace_back([&] {
+                for (size_t i = next++; i < to_compile.size(); i = next++)
+                    (void)compile_direct(to_compile[i].first, to_compile[i].second, 1, 1, dev.arch, nullptr, nullptr,
+                                         true);
+            });
+        for (auto& th : pool) th.join();
+        clear_error();
+        if (o.verbose) std::fprintf(stderr, "[batch tune] %zu candidates compiled\n", to_compile.size());
+    }
+
     int g = 0;
-    for (const auto& kv : by_filter) {
-        const int fh = kv.first.first, fw = kv.first.second;
+    for (const auto& kv : groups) {
+        const int fh = std::get<0>(kv.first), fw = std::get<1>(kv.first), bk = std::get<2>(kv.first);
         GroupBench gb;
         gb.shapes = kv.second;
         rc = gb.init();
         if (rc) return rc;
-        const conv2d_config current = batch_config_for_filter(dev, wp, fh, fw);
-        std::vector<conv2d_config> cands{current};
-        for (const auto& c : sweep_leaders(dev, rdir, fh, fw, o.candidates)) {
-            bool seen = false;
-            for (const auto& e : cands) seen = seen || config_equal(e, c);
-            if (!seen) cands.push_back(c);
-        }
+        const std::vector<conv2d_config>& cand = cands[(size_t)g];
         std::vector<RecordT<conv2d_config>> timed;
         double current_ms = 0;
-        for (size_t k = 0; k < cands.size(); ++k) {
-            conv2d_config c = cands[k];
+        for (size_t k = 0; k < cand.size(); ++k) {
+            conv2d_config c = cand[k];
             Module m;
-            if (build_module(conv2d_shape{4096, 4096, fh, fw}, &c, 1, 1, dev.arch, true, true, &m) != CONV2D_OK) {
+            if (batch_module(dev, fh, fw, &c, &m) != CONV2D_OK) {
                 clear_error();
                 continue;
             }
@@ -607,7 +694,8 @@ extern "C" int conv2d_batch_tune(int n, const conv2d_shape* shapes, const conv2d
             if (k == 0) current_ms = ms;
             timed.push_back(RecordT<conv2d_config>{c, kOk, ms, ms, ms, o.reps});
             if (o.verbose)
-                std::fprintf(stderr, "[batch tune] %dx%d %s: %.4f ms\n", fh, fw, config_str(c).c_str(), ms);
+                std::fprintf(stderr, "[batch tune] %dx%d bucket %d (%zu problems) %s: %.4f ms\n", fh, fw, bk,
+                             kv.second.size(), config_str(c).c_str(), ms);
         }
         if (timed.empty()) return fail(CONV2D_EVERIFY, "batch tune: no configuration ran and verified");
         std::sort(timed.begin(), timed.end(), [](const auto& a, const auto& b) {
@@ -616,12 +704,14 @@ extern "C" int conv2d_batch_tune(int n, const conv2d_shape* shapes, const conv2d
         RecordT<conv2d_config> win = timed[0];
         for (const auto& r : timed)
             if (r.ms <= timed[0].ms * (1.0 + o.tie_rel) && config_less(r.c, win.c)) win = r;
-        rc = cache_store(wp, dev.arch, batch_key(fh, fw), win.c, win.ms);
+        rc = cache_store(wp, dev.arch, batch_key(fh, fw, bk), win.c, win.ms);
         if (rc) return rc;
         if (g < CONV2D_BATCH_TUNE_MAX) {
             res->filt[2 * g] = fh;
             res->filt[2 * g + 1] = fw;
-            res->before[g] = current;
+            res->bucket[g] = bk;
+            res->n_problems[g] = (int)kv.second.size();
+            res->before[g] = cand[0];
             res->after[g] = win.c;
             res->before_ms[g] = current_ms;
             res->after_ms[g] = win.ms;

@@ -139,10 +139,16 @@ struct ConvDesc {
 };
 static_assert(sizeof(ConvDesc) == 48, "descriptor layout must match the kernel");
 
-// The tuned configuration for a filter size (4096x4096 entry of the winners
-// cache, else any entry with that filter, else the default; filter always read
-// through its pointer) and its compiled, loaded batched module.
-int batch_module_for_filter(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m);
+// Size bucket (1..CONV2D_SIZE_BUCKETS) of a problem for the batched path.
+int size_bucket(int out_h, int out_w);
+// The batched kernel's configuration for filter fh x fw from the winners
+// cache: size bucket `bucket`'s entry, else the whole-batch entry (bucket 0:
+// the whole-batch entry, else bucket `fallback_bucket`'s), else the 4096x4096
+// winner, else the default; filter through its pointer.
+conv2d_config batch_config_for(const DeviceInfo& dev, int fh, int fw, int bucket, int fallback_bucket = 0);
+// Compiles and loads the batched kernel of a configuration (the rolled row
+// loop replaces one that spills; cfg->unroll then becomes 1).
+int batch_module(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m);
 // Launches a batched kernel over `total_tiles` tiles on `grid` workgroups.
 int launch_batch_kernel(const Module& m, const conv2d_config& cfg, int grid, const void* d_desc,
                         const void* d_owner, int total_tiles, hipStream_t st);

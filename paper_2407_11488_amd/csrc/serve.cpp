@@ -7,7 +7,8 @@
 // in for an image that arrives in HBM). Whenever one of K streams is free, all
 // admitted requests not yet launched (up to max_batch) go out as one batch:
 // one fill launch for every image and filter of the batch, then one
-// batched kernel per filter size present. Batches on different
+// batched kernel per filter size and configuration present (each request
+// takes its filter size's and size bucket's tuned configuration). Batches on different
 // streams overlap on the device; completion is observed with events, and each
 // request's latency runs from its arrival to the host seeing its batch done.
 //
@@ -92,9 +93,11 @@ struct Req {
     size_t n_in = 0, n_f = 0, n_out = 0;
     double t_launch = 0, t_done = 0;
     bool stalled = false;
+    int kernel = -1;   // batched kernel of the request (index into the server's kernels)
 };
 
 struct FilterKernel {
+    int fh = 0, fw = 0;
     conv2d_config cfg{};
     Module mod;
 };
@@ -131,7 +134,7 @@ public:
             if (s.h_tab) hipHostFree(s.h_tab);
             if (s.d_tab) hipFree(s.d_tab);
         }
-        for (auto& kv : kernels_) unload_module(&kv.second.mod);
+        for (auto& k : kernels_) unload_module(&k.mod);
         for (auto& kv : direct_) unload_module(&kv.second);
     }
 
@@ -155,16 +158,29 @@ public:
                 return fail(CONV2D_EINVAL, "request " + std::to_string(i) + " alone exceeds the HBM budget");
             if (i > 0 && rq_[i].arrival_s < rq_[i - 1].arrival_s)
                 return fail(CONV2D_EINVAL, "arrival times must be non-decreasing");
-            // Kernels for every filter size of the trace are built up front.
-            const auto key = std::make_pair(s.filt_h, s.filt_w);
-            if (!o_.serial_plain && !kernels_.count(key)) {
-                FilterKernel fk;
-                rc = batch_module_for_filter(dev_, s.filt_h, s.filt_w, &fk.cfg, &fk.mod);
-                if (rc) return rc;
-                kernels_.emplace(key, fk);
-            }
+            // Kernels for every filter size and size bucket of the trace are
+            // built up front (buckets that share a configuration share one).
             if (!o_.serial_plain) {
-                const conv2d_config& c = kernels_[key].cfg;
+                const auto bkey = std::make_tuple(s.filt_h, s.filt_w, size_bucket(s.out_h, s.out_w));
+                auto it = kernel_of_bucket_.find(bkey);
+                if (it == kernel_of_bucket_.end()) {
+                    const conv2d_config c = batch_config_for(dev_, s.filt_h, s.filt_w, std::get<2>(bkey), 0);
+                    const auto ckey = std::make_pair(std::make_pair(s.filt_h, s.filt_w), config_str(c));
+                    auto jt = kernel_of_cfg_.find(ckey);
+                    if (jt == kernel_of_cfg_.end()) {
+                        FilterKernel fk;
+                        fk.fh = s.filt_h;
+                        fk.fw = s.filt_w;
+                        fk.cfg = c;
+                        rc = batch_module(dev_, s.filt_h, s.filt_w, &fk.cfg, &fk.mod);
+                        if (rc) return rc;
+                        kernels_.push_back(fk);
+                        jt = kernel_of_cfg_.emplace(ckey, (int)kernels_.size() - 1).first;
+                    }
+                    it = kernel_of_bucket_.emplace(bkey, jt->second).first;
+                }
+                req_[i].kernel = it->second;
+                const conv2d_config& c = kernels_[(size_t)it->second].cfg;
                 max_tiles_per_req = std::max(max_tiles_per_req, (size_t)geometry(s.out_h, s.out_w, c).n_tiles);
             }
         }
@@ -290,11 +306,11 @@ private:
             int tiles;
         };
         std::vector<G> groups;
-        std::map<std::pair<int, int>, std::vector<int>> by_filter;
-        for (int i : batch) by_filter[{rq_[i].shape.filt_h, rq_[i].shape.filt_w}].push_back(i);
+        std::map<int, std::vector<int>> by_kernel;
+        for (int i : batch) by_kernel[req_[i].kernel].push_back(i);
         size_t nd = 0, no = 0;
-        for (auto& kv : by_filter) {
-            const FilterKernel& fk = kernels_.at(kv.first);
+        for (auto& kv : by_kernel) {
+            const FilterKernel& fk = kernels_.at((size_t)kv.first);
             G g{&fk, nd, kv.second.size(), no, 0};
             for (size_t k = 0; k < kv.second.size(); ++k) {
                 const int i = kv.second[k];
@@ -465,7 +481,9 @@ private:
     conv2d_serve_opts o_;
     DeviceInfo dev_;
     std::vector<Req> req_;
-    std::map<std::pair<int, int>, FilterKernel> kernels_;
+    std::vector<FilterKernel> kernels_;
+    std::map<std::tuple<int, int, int>, int> kernel_of_bucket_;
+    std::map<std::pair<std::pair<int, int>, std::string>, int> kernel_of_cfg_;
     std::map<std::pair<int, int>, conv2d_config> direct_cfg_;
     std::map<std::tuple<int, int, int, int>, Module> direct_;
     Arena arena_;

@@ -14,6 +14,14 @@ The batched path's configurations on the 64-problem uneven workload (each
 filter size's fastest 4096x4096 sweep points, timed as that size's batched
 kernel over the batch's problems; stored as the (0, 0, fh, fw) winners):
     python -m paper_2407_11488_amd.tune --batch [--candidates 12]
+The served path's configurations per filter size and size bucket (sizes up
+to 384, 768, 1536, 3072 and above), tuned on a sample of shapes drawn like the
+served workload's, stored as the (0, bucket, fh, fw) winners:
+    python -m paper_2407_11488_amd.tune --buckets [--sample 160]
+The server's stream count and batch-size cap (streams 1-8 x caps 1-256, each
+serving one Poisson trace at a fraction of serial capacity; lowest p99 wins),
+stored in tuned/serve_params.json:
+    python -m paper_2407_11488_amd.tune --serving [--rate 0.8 --duration 3]
 
 Hotspot stencil (the second tunable kernel), one grid and step count:
     python -m paper_2407_11488_amd.tune --hotspot 4096 4096 --steps 60 [--results PATH]
@@ -138,18 +146,37 @@ def main(argv=None) -> int:
     ap.add_argument("--hotspot", type=int, nargs=2, metavar=("ROWS", "COLS"))
     ap.add_argument("--batch", action="store_true")
     ap.add_argument("--candidates", type=int, default=12)
+    ap.add_argument("--buckets", action="store_true",
+                    help="batched kernels per filter size and size bucket, on a sample of served shapes")
+    ap.add_argument("--sample", type=int, default=160)
+    ap.add_argument("--serving", action="store_true",
+                    help="the server's stream count and batch-size cap, by p99 on a trace of its own")
+    ap.add_argument("--rate", type=float, default=0.8, help="--serving: load as a fraction of serial capacity")
+    ap.add_argument("--duration", type=float, default=3.0, help="--serving: trace seconds per point")
     ap.add_argument("--steps", type=int, default=60)
     a = ap.parse_args(argv)
 
-    if a.batch:
+    if a.serving:
+        from . import workloads
+        emit(workloads.tune_serving(a.rate, a.duration), a.json)
+        return 0
+    if a.batch or a.buckets:
         import datagen
         o = B.conv2d_batch_tune_defaults()
         o.winners_path = a.winners.encode()
         o.results_dir = (a.results_dir or os.path.dirname(DEFAULT_WINNERS)).encode()
         o.candidates, o.verbose = a.candidates, 1
-        r = B.conv2d_batch_tune(datagen.batch_shapes(64), o)
-        emit({"workload": "batched, 64 problems (sides log-uniform [256, 2048], filters {3,5,9,17})",
-              "groups": r.groups()}, a.json)
+        if a.buckets:
+            # one configuration per filter size and size bucket, tuned on a
+            # sample of the served distribution
+            o.buckets = 1
+            shapes = datagen.serving_sample(a.sample)
+            what = f"{a.sample} request shapes like the served workload's (sides log-uniform [128, 4096])"
+        else:
+            shapes = datagen.batch_shapes(64)
+            what = "batched, 64 problems (sides log-uniform [256, 2048], filters {3,5,9,17})"
+        r = B.conv2d_batch_tune(shapes, o)
+        emit({"workload": what, "groups": r.groups()}, a.json)
         return 0
     if a.hotspot:
         rows, cols = a.hotspot

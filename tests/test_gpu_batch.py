@@ -94,6 +94,20 @@ def test_graph_replays_and_pointer_changes(workload):
     for a, o in zip(first, outs2):
         assert np.array_equal(a.view(np.uint32), o.cpu().numpy().view(np.uint32))
     direct.close()
+    # the bound form: tensors checked once, then repeated runs on them
+    again = C.Batch(sub)
+    outs3 = [torch.full((H, W), float("nan"), device="cuda") for (H, W, _, _) in sub]
+    with pytest.raises(ValueError):
+        again.bind([ins[k] for k in sel], [fs[k] for k in sel], outs3[1:] + outs3[:1])
+    run = again.bind([ins[k] for k in sel], [fs[k] for k in sel], outs3)
+    for _ in range(3):
+        for o in outs3:
+            o.fill_(float("nan"))
+        run()
+        torch.cuda.synchronize()
+        for a, o in zip(first, outs3):
+            assert np.array_equal(a.view(np.uint32), o.cpu().numpy().view(np.uint32))
+    again.close()
 
 
 def test_batch_edge_cases():
@@ -154,13 +168,8 @@ def test_batch_errors():
         C.conv2d_batch_destroy(b)
 
 
-def test_batch_tune_stores_and_is_used(tmp_path, monkeypatch):
-    """conv2d_batch_tune on a small two-filter batch: every filter size gets a
-    verified winner no slower than the current choice, stored as the
-    (0, 0, fh, fw) entry; a batch planned afterwards uses it, and its outputs
-    still match the oracle."""
+def _tune_env(tmp_path):
     import shutil
-    torch = torch_cuda()
     wp = tmp_path / "winners.jsonl"
     here = os.path.join(os.path.dirname(C.LIB_PATH), "tuned")
     shutil.copy(os.path.join(here, "winners.jsonl"), wp)
@@ -168,6 +177,27 @@ def test_batch_tune_stores_and_is_used(tmp_path, monkeypatch):
         src = os.path.join(here, f"results_gfx950_4096x4096_{f}x{f}.jsonl")
         if os.path.exists(src):
             shutil.copy(src, tmp_path / os.path.basename(src))
+    return wp
+
+
+def _check_batch_matches_oracle(torch, b, shapes, base):
+    ins, fs = zip(*[_device_problem(torch, s, base + p) for p, s in enumerate(shapes)])
+    outs = b(list(ins), list(fs))
+    torch.cuda.synchronize()
+    for p, (H, W, fh, fw) in enumerate(shapes):
+        inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=datagen.SEED_BATCH_INPUT_BASE + base + p,
+                                      seed_f=datagen.SEED_BATCH_FILTER_BASE + base + p)
+        ref, s = oracle.conv2d_f64(inp, f)
+        assert oracle.normalized_error(outs[p].cpu().numpy(), ref, s) <= TOL, p
+
+
+def test_batch_tune_stores_and_is_used(tmp_path, monkeypatch):
+    """conv2d_batch_tune on a small two-filter batch: every filter size gets a
+    verified winner no slower than the current choice, stored as the
+    (0, 0, fh, fw) entry; a batch planned afterwards uses it, and its outputs
+    still match the oracle."""
+    torch = torch_cuda()
+    wp = _tune_env(tmp_path)
     shapes = [(300, 300, 9, 9), (200, 260, 9, 9), (150, 150, 3, 3), (520, 400, 3, 3)]
     o = C.conv2d_batch_tune_defaults()
     o.winners_path = str(wp).encode()
@@ -178,7 +208,7 @@ def test_batch_tune_stores_and_is_used(tmp_path, monkeypatch):
     say(f"batch tune: {groups}")
     assert r.n_groups == 2
     for g in groups:
-        assert g["tried"] >= 1 and g["after_ms"] > 0
+        assert g["tried"] >= 1 and g["after_ms"] > 0 and g["bucket"] == 0
         assert g["after_ms"] <= g["before_ms"] * (1 + o.tie_rel) + 1e-9
         got = C.conv2d_cache_lookup(str(wp), None, C.shape(0, 0, *g["filter"]))[0].tuple()
         assert got == tuple(g["after"])
@@ -186,14 +216,48 @@ def test_batch_tune_stores_and_is_used(tmp_path, monkeypatch):
     b = C.Batch(shapes)
     used = {tuple(x["filter"]): tuple(x["config"]) for x in b.info["groups"]}
     for g in groups:
-        want = tuple(g["after"])
-        assert used[tuple(g["filter"])][:6] == want[:6]      # the build may roll the row loop
-    ins, fs = zip(*[_device_problem(torch, s, 90 + p) for p, s in enumerate(shapes)])
-    outs = b(list(ins), list(fs))
-    torch.cuda.synchronize()
-    for p, (H, W, fh, fw) in enumerate(shapes):
-        inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=datagen.SEED_BATCH_INPUT_BASE + 90 + p,
-                                      seed_f=datagen.SEED_BATCH_FILTER_BASE + 90 + p)
-        ref, s = oracle.conv2d_f64(inp, f)
-        assert oracle.normalized_error(outs[p].cpu().numpy(), ref, s) <= TOL
+        assert used[tuple(g["filter"])][:6] == tuple(g["after"])[:6]   # the build may roll the row loop
+    _check_batch_matches_oracle(torch, b, shapes, 90)
     b.close()
+
+
+def test_batch_tune_by_size_bucket(tmp_path, monkeypatch):
+    """With buckets on, one entry (0, b, fh, fw) per filter size and size
+    bucket; a CONV2D_BATCH_BY_SIZE batch planned afterwards gives each problem
+    its bucket's configuration (one kernel per distinct filter and
+    configuration) and still matches the oracle, a problem of a bucket with no
+    entry falling back to the filter's other entries; a plain batch keeps one
+    kernel per filter size, its whole-batch entry."""
+    torch = torch_cuda()
+    wp = _tune_env(tmp_path)
+    tuned = [(200, 200, 9, 9), (300, 260, 9, 9), (1100, 900, 9, 9), (150, 150, 3, 3), (700, 600, 3, 3)]
+    o = C.conv2d_batch_tune_defaults()
+    o.winners_path = str(wp).encode()
+    o.results_dir = str(tmp_path).encode()
+    o.candidates, o.reps, o.buckets = 3, 5, 1
+    r = C.conv2d_batch_tune(tuned, o)
+    groups = r.groups()
+    say(f"bucket tune: {groups}")
+    assert sorted((g["filter"][0], g["bucket"], g["problems"]) for g in groups) == \
+        [(3, 1, 1), (3, 2, 1), (9, 1, 2), (9, 3, 1)]
+    for g in groups:
+        got = C.conv2d_cache_lookup(str(wp), None, C.shape(0, g["bucket"], *g["filter"]))[0].tuple()
+        assert got == tuple(g["after"])
+    monkeypatch.setenv("CONV2D_WINNERS", str(wp))
+    shapes = tuned + [(2000, 1800, 9, 9)]          # bucket 4 of 9x9 has no entry of its own
+    b = C.Batch(shapes, flags=C.CONV2D_BATCH_BY_SIZE)
+    info = b.info["groups"]
+    want = {(g["filter"][0], tuple(g["after"])[:6]) for g in groups}
+    have = {(x["filter"][0], tuple(x["config"])[:6]) for x in info}
+    assert want <= have                                               # every bucket's winner is used
+    assert len(info) == len({(x["filter"][0], tuple(x["config"])) for x in info})   # one kernel per config
+    _check_batch_matches_oracle(torch, b, shapes, 120)
+    b.close()
+    # without the flag, a filter's whole-batch entry wins: one kernel per filter
+    whole = C.Batch(shapes)
+    assert sorted(x["filter"][0] for x in whole.info["groups"]) == [3, 9]
+    for x in whole.info["groups"]:
+        got = C.conv2d_cache_lookup(str(wp), None, C.shape(0, 0, *x["filter"]))
+        if got is not None:
+            assert tuple(x["config"])[:6] == got[0].tuple()[:6]
+    whole.close()

@@ -297,3 +297,16 @@ def test_hotspot_code_is_plain_fp32_without_spills(cfg):
     n = _notes(path)
     assert n["private_segment_fixed_size"] == 0 and n["vgpr_spill_count"] == 0
     assert 0 < n["group_segment_fixed_size"] <= C.hotspot_lds_bytes(cfg)
+
+
+def test_serving_tuner_pick():
+    """The server-parameter tuner's choice: lowest p99, p99s within 2 % tie,
+    ties to the lowest p50, then fewer streams, then the smaller cap."""
+    from paper_2407_11488_amd.workloads import pick_serving
+    t = [{"streams": 4, "max_batch": 64, "p50_ms": 0.05, "p99_ms": 0.300},
+         {"streams": 2, "max_batch": 16, "p50_ms": 0.04, "p99_ms": 0.305},
+         {"streams": 8, "max_batch": 16, "p50_ms": 0.04, "p99_ms": 0.303},
+         {"streams": 1, "max_batch": 1, "p50_ms": 0.02, "p99_ms": 0.400}]
+    assert pick_serving(t) == t[1]                      # tie on p99 and p50: fewer streams
+    assert pick_serving(t, tie_rel=0.0) == t[0]         # no ties: strictly lowest p99
+    assert pick_serving(t[3:]) == t[3]
