@@ -137,6 +137,29 @@ def test_unroll_and_alignment_variants(cfg):
     assert np.array_equal(got.cpu().numpy().view(np.uint32), out.cpu().numpy().view(np.uint32))
 
 
+@pytest.mark.parametrize("fh,fw", [(63, 63), (1, 63), (63, 1)])
+def test_largest_filters_integer_bitwise(fh, fw):
+    """The largest filters the library accepts (63 taps a side), constant and
+    global filter placement, with and without LDS: integer data keeps every
+    partial sum an integer below 2^24 (63*63*16 < 2^16), so each output equals
+    the oracle bit for bit."""
+    H, W = 70, 90
+    s = C.shape(H, W, fh, fw)
+    cfgs = [c for c in [(64, 1, 1, 1, 0, 0, 1), (16, 16, 2, 2, 1, 0, 1), (32, 4, 4, 2, 0, 1, 1),
+                        (128, 2, 2, 4, 1, 1, 1)] if C.conv2d_config_check(s, c) == 0]
+    assert len(cfgs) >= 3
+    precompile(C, s, cfgs, vec_class(W + fw - 1), vec_class(W))
+    inp, f = datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=41, seed_f=42)
+    ref, _ = oracle.conv2d_f64(inp, f)
+    di, df = to_dev(inp), to_dev(f)
+    for c in cfgs:
+        say(f"largest filter {fh}x{fw} cfg {c}")
+        got = run_config(C, di, df, c).cpu().numpy().astype(np.float64)
+        assert np.array_equal(got, ref), c
+    with pytest.raises(C.Conv2dError):
+        C.conv2d_plan(C.shape(H, W, fh + (fh == 63), fw + (fw == 63)), None)
+
+
 @pytest.mark.parametrize("fsize", [17, 3, 5, 7, 9, 15, 31])
 def test_full_size_sampled(fsize):
     """4096x4096 outputs with each filter of the filter-size sweep, in the
