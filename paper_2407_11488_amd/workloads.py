@@ -48,6 +48,28 @@ def tuned_config_for_filter(fh, fw):
     return c if c is not None else B.conv2d_default_config().tuple()
 
 
+WARM_MS = 25.0
+
+
+def warm_up(fn, stream, min_ms: float = WARM_MS, at_least: int = 3, at_most: int = 2000) -> int:
+    """Runs fn() until at least `min_ms` of GPU time (HIP events on
+    `stream`) and `at_least` calls have passed: after its set-up the GPU
+    idles at a lower clock, and about 20 ms of work brings it to the steady
+    state that the timed calls are meant to measure. Returns the call count."""
+    torch = _torch()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    done, spent = 0, 0.0
+    while done < at_most and (done < at_least or spent < min_ms):
+        e0.record(stream)
+        for _ in range(at_least):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        done += at_least
+        spent += e0.elapsed_time(e1)
+    return done
+
+
 def batch_benchmark(reps: int = 20, warmup: int = 3, n: int = 64) -> dict:
     torch = _torch()
     from .api import Batch, Plan
@@ -68,9 +90,7 @@ def batch_benchmark(reps: int = 20, warmup: int = 3, n: int = 64) -> dict:
     torch.cuda.synchronize()
 
     def timed(fn, k):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
+        warm_up(fn, st, at_least=warmup)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(st)
@@ -233,9 +253,7 @@ def hotspot_benchmark(reps: int = 20, warmup: int = 3, steps: int = 60, rows: in
     res = {"workload": f"hotspot chip {rows}x{cols}, {steps} steps", "steps": steps}
     for name, cfg in (("plan", None), ("default", B.hotspot_default_config().tuple())):
         plan = Hotspot(rows, cols, cfg)
-        for _ in range(warmup):
-            plan(td, pd, steps, k, out=out)
-        torch.cuda.synchronize()
+        warm_up(lambda: plan(td, pd, steps, k, out=out), st, at_least=warmup)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         for _ in range(reps):
