@@ -144,7 +144,12 @@ int conv2d_plan_config(conv2d_plan_t plan, conv2d_config *cfg, int *tuned);
 
 /* Enqueues one convolution on `stream`. With filter_in_const = 1 the filter is
  * first copied (device to device, on the same stream) into the module's
- * constant array: such a plan must not run concurrently on two streams. */
+ * constant array: such a plan must not run concurrently on two streams. The
+ * call may be recorded by stream capture into a graph (a copy node, when the
+ * filter goes to constant memory, then the kernel node); replays read the
+ * buffers' current contents. Capture a call whose pointers are aligned as the
+ * plan's first run will be, or run it once first: the first misaligned call
+ * compiles a second module. */
 int conv2d_run(conv2d_plan_t plan, const float *d_in, const float *d_filter, float *d_out,
                void *stream);
 
