@@ -83,24 +83,50 @@ def time_plan(torch, C, plan, d_in, d_f, d_out, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(seconds: float):
-    """The FP64 oracle on the same 4096x4096 / 17x17 problem, repeated until
-    about `seconds` of CPU time have passed."""
-    import datagen
-    import oracle
-    inp, f = datagen.conv_problem(H, W, FH, FW)
-    flops = 2.0 * H * W * FH * FW
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle(oracle, inp, f, seconds: float, max_runs: int):
     t0 = time.perf_counter()
     runs = 0
     while True:
         oracle.conv2d_f64(inp, f, with_abs=False)
         runs += 1
         el = time.perf_counter() - t0
-        if el >= seconds or runs >= 50:
-            break
-    return {"value": round(flops * runs / el / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"the whole 4096x4096/17x17 problem (FP64, OpenMP over rows), {runs} run(s), {el:.1f} s"}
+        if el >= seconds or runs >= max_runs:
+            return runs, el
+
+
+def cpu_baseline(seconds: float):
+    """The FP64 oracle on the same 4096x4096 / 17x17 problem with all host
+    threads, repeated until about `seconds` have passed; and, single-threaded,
+    on the 1024x1024 / 17x17 plain workload (zero halo) for a few seconds."""
+    import datagen
+    import oracle
+    threads = oracle.num_threads()
+    inp, f = datagen.conv_problem(H, W, FH, FW)
+    flops = 2.0 * H * W * FH * FW
+    runs, el = _time_oracle(oracle, inp, f, seconds, 50)
+    out = {"value": round(flops * runs / el / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"the whole 4096x4096/17x17 problem (FP64, OpenMP over rows), {runs} run(s), {el:.1f} s",
+           "cpu_model": host_cpu_model(), "host_threads": os.cpu_count()}
+    small_in, small_f = datagen.conv_problem(1024, 1024, FH, FW, zero_halo=True)
+    oracle.set_num_threads(1)
+    try:
+        r1, e1 = _time_oracle(oracle, small_in, small_f, min(seconds / 3, 5.0), 30)
+    finally:
+        oracle.set_num_threads(threads)
+    out["single_thread_1024x1024"] = {"value": round(2.0 * 1024 * 1024 * FH * FW * r1 / e1 / 1e9, 3),
+                                      "unit": "GFLOP/s", "cores": 1, "runs": r1, "seconds": round(e1, 2)}
+    return out
 
 
 def main():

@@ -59,6 +59,8 @@ def _load():
         for fn in (lib.oracle_conv2d_f64, lib.oracle_conv2d_points_f64, lib.oracle_conv2d_rows_f64):
             fn.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         D = ctypes.c_double
         lib.oracle_hotspot_f64.argtypes = [fp, fp, L, L, L, D, D, D, D, D, dp]
         lib.oracle_hotspot_f64.restype = ctypes.c_int
@@ -128,6 +130,11 @@ def conv2d_rows_f64(inp, filt, y0: int, y1: int):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle calls (timing only; results do not change)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def normalized_error(gpu, ref, abs_sum):
