@@ -219,7 +219,8 @@ def main():
         sv = workloads.serve_benchmark(duration=args.serve_seconds, rates=(0.8,))
         run = sv["runs"][0]
         line["serving"] = {"workload": sv["workload"], "duration_s": sv["duration_s"],
-                           "rate_req_s": run["rate_req_s"], "serial_capacity_req_s": sv["serial_capacity_req_s"],
+                           "hbm_budget_gib": sv["hbm_budget_gib"], "streams": sv["streams"],
+                           "max_batch": sv["max_batch"], "rate_req_s": run["rate_req_s"], "serial_capacity_req_s": sv["serial_capacity_req_s"],
                            "batched_capacity_req_s": sv["batched_capacity_req_s"],
                            "p50_ms": run["batched"]["p50_ms"], "p99_ms": run["batched"]["p99_ms"],
                            "req_per_s": run["batched"]["req_per_s"], "gflops": run["batched"]["gflops"],

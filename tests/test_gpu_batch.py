@@ -150,6 +150,26 @@ def test_batch_many_filter_sizes():
     b.close()
 
 
+def test_batch_integer_data_bitwise():
+    """Integer data (inputs and filters in [-4, 4]) keeps every partial sum an
+    exact integer, so each output of an uneven batch over all four filter
+    sizes equals the FP64 oracle bit for bit."""
+    torch = torch_cuda()
+    shapes = [(300, 257, 17, 17), (77, 401, 9, 9), (256, 256, 5, 5), (129, 65, 3, 3), (1, 1, 17, 17),
+              (520, 33, 9, 9), (33, 520, 3, 3), (1000, 3, 5, 5)]
+    probs = [datagen.conv_problem(*s, kind="int", seed_in=300 + k, seed_f=400 + k) for k, s in enumerate(shapes)]
+    b = C.Batch(shapes)
+    ins = [torch.from_numpy(i).cuda() for i, _ in probs]
+    fs = [torch.from_numpy(f).cuda() for _, f in probs]
+    outs = [torch.full((H, W), float("nan"), device="cuda") for (H, W, _, _) in shapes]
+    b(ins, fs, outs)
+    torch.cuda.synchronize()
+    for k, (inp, f) in enumerate(probs):
+        ref, _ = oracle.conv2d_f64(inp, f)
+        assert np.array_equal(outs[k].cpu().numpy().astype(np.float64), ref), shapes[k]
+    b.close()
+
+
 def test_batch_errors():
     torch = torch_cuda()
     with pytest.raises(C.Conv2dError):
