@@ -130,8 +130,10 @@ int conv2d_cache_store(const char *path, const char *arch, conv2d_shape s,
 /* ---------------------------------------------------------------- plain path */
 
 /* Creates a plan for one shape on the current device. cfg = NULL takes the
- * tuned winner from the winners cache (env CONV2D_WINNERS, else the
- * tuned/winners.jsonl file beside this library), else the default
+ * tuned winner for this shape from the winners cache (env CONV2D_WINNERS,
+ * else the tuned/winners.jsonl file beside this library), else the winner of
+ * the same filter size for another shape (4096 x 4096 first, else the most
+ * recent) when it is legal for this shape, else the default
  * configuration; the environment variable CONV2D_FORCE_CONFIG
  * ("bx,by,tx,ty,lds,const,unroll") overrides both. Compiles (or loads from the
  * code-object cache) and loads the module. The plan owns the module. */
@@ -139,7 +141,8 @@ int conv2d_plan(conv2d_plan_t *plan, conv2d_shape s, const conv2d_config *cfg);
 
 /* The configuration a plan uses, and whether it came from the winners cache
  * (*tuned = 1; 3 when that entry was tuned with an older revision of the
- * kernel source), was forced or given (2), or is the default (0). */
+ * kernel source; 4 when it is the same filter's winner for another shape),
+ * was forced or given (2), or is the default (0). */
 int conv2d_plan_config(conv2d_plan_t plan, conv2d_config *cfg, int *tuned);
 
 /* Enqueues one convolution on `stream`. With filter_in_const = 1 the filter is

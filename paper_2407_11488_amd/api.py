@@ -36,7 +36,8 @@ class Plan:
         self.handle = B.conv2d_plan(self.shape, config)
         cfg, src = B.conv2d_plan_config(self.handle)
         self.config = cfg.tuple()
-        self.source = {0: "default", 1: "tuned", 2: "given", 3: "tuned-older-kernel"}.get(src, str(src))
+        self.source = {0: "default", 1: "tuned", 2: "given", 3: "tuned-older-kernel",
+                       4: "tuned-other-shape"}.get(src, str(src))
 
     def __call__(self, inp, filt, out=None, stream=None):
         torch = _torch()

@@ -255,6 +255,12 @@ extern "C" int conv2d_plan(conv2d_plan_t* plan, conv2d_shape s, const conv2d_con
         bool stale = false;
         if (cache_lookup(wp, dev.arch, s, &p->cfg, &ms, &stale) == CONV2D_OK) {
             p->source = stale ? 3 : 1;
+        } else if (cache_lookup_filter(wp, dev.arch, s.filt_h, s.filt_w, conv2d_shape{4096, 4096, s.filt_h, s.filt_w},
+                                       &p->cfg) == CONV2D_OK &&
+                   conv2d_config_check(s, &p->cfg, dev.lds_limit) == CONV2D_OK) {
+            // No entry for this shape: the same filter's winner for another
+            // shape (4096 x 4096 first) usually beats the default by far.
+            p->source = 4;
         } else {
             conv2d_default_config(&p->cfg);
             p->source = 0;

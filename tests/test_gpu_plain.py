@@ -188,6 +188,66 @@ def test_full_size_sampled(fsize):
     plan.close()
 
 
+def test_input_above_2gib_runs_in_bands():
+    """An input above 2 GiB (output 24000 x 24000, 3 x 3 filter: 2.3 GB) runs
+    as several launches over horizontal bands (32-bit buffer offsets): sampled
+    outputs on both sides of every band boundary, at the corners and inside
+    match the oracle, each computed from the generator's values of its own
+    window; every sampled output finite."""
+    torch = torch_cuda()
+    H = W = 24000
+    fh = fw = 3
+    P = W + fw - 1
+    n_in = (H + fh - 1) * P
+    assert 4 * n_in > 2**31
+    st = torch.cuda.current_stream().cuda_stream
+    d_in = torch.empty(n_in, dtype=torch.float32, device="cuda")
+    d_f = torch.empty(fh * fw, dtype=torch.float32, device="cuda")
+    C.conv2d_fill_uniform(d_in.data_ptr(), n_in, 61, 0, st)
+    C.conv2d_fill_uniform(d_f.data_ptr(), fh * fw, 62, 0, st)
+    plan = C.Plan(H, W, fh, fw)
+    say(f"banded 24000x24000 f3 with {plan.source} config {plan.config}")
+    out = torch.full((H, W), float("nan"), dtype=torch.float32, device="cuda")
+    C.conv2d_run(plan.handle, d_in.data_ptr(), d_f.data_ptr(), out.data_ptr(), st)
+    torch.cuda.synchronize()
+    rows = (2**31 - 1) // (4 * P) - (fh - 1)          # output rows per band
+    assert rows < H
+    bounds = list(range(rows, H, rows))
+    rng = np.random.default_rng(7)
+    ys = [0, 0, H - 1, H - 1] + [b + d for b in bounds for d in (-2, -1, 0, 1)] + list(rng.integers(0, H, 40))
+    xs = [0, W - 1, 0, W - 1] + [int(v) for v in rng.integers(0, W, 4 * len(bounds))] + list(rng.integers(0, W, 40))
+    f = datagen.uniform_pm1(62, fh * fw).reshape(fh, fw)
+    for y, x in zip(ys, xs):
+        win = np.stack([datagen.uniform_pm1(61, fw, start=(y + i) * P + x) for i in range(fh)])
+        ref, sabs = oracle.conv2d_f64(win, f)
+        v = out[y, x].item()
+        assert np.isfinite(v), (y, x)
+        assert oracle.normalized_error(np.array([[v]], np.float32), ref, sabs) <= TOL, (y, x)
+    plan.close()
+    del out, d_in
+
+
+def test_untuned_shape_takes_the_filters_winner(tmp_path, monkeypatch):
+    """A shape with no winners entry of its own takes the same filter's
+    4096 x 4096 winner (source "tuned-other-shape"); a filter with no entry
+    at all takes the default; either way the result matches the oracle."""
+    torch = torch_cuda()
+    wp = tmp_path / "winners.jsonl"
+    cfg = (64, 2, 4, 4, 1, 0, 1)
+    C.conv2d_cache_store(str(wp), "gfx950", C.shape(4096, 4096, 9, 9), cfg, 1.0)
+    monkeypatch.setenv("CONV2D_WINNERS", str(wp))
+    for (H, W, fh, fw), want in (((300, 260, 9, 9), ("tuned-other-shape", cfg)),
+                                 ((300, 260, 7, 7), ("default", C.conv2d_default_config().tuple()))):
+        plan = C.Plan(H, W, fh, fw)
+        say(f"untuned {H}x{W} f{fh}: {plan.source} {plan.config}")
+        assert (plan.source, tuple(plan.config)) == want
+        inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=71, seed_f=72)
+        out = plan(to_dev(inp), to_dev(f))
+        torch.cuda.synchronize()
+        _check_uniform(out, inp, f)
+        plan.close()
+
+
 def test_errors_are_reported_not_faulted():
     torch = torch_cuda()
     s = C.shape(64, 64, 5, 5)
