@@ -200,3 +200,100 @@ def base_space_times(db: str, shape, unroll: int = 1) -> dict:
     keyed by the 6-parameter tuple."""
     return {c[:6]: r["ms"] for c, r in load(db, shape).items()
             if r.get("status") == "ok" and r.get("ms", 0) > 0 and c[6] == unroll}
+
+
+# ---------------------------------------------------------------- local-search effort
+
+def local_search_effort(times: dict, shape, ps=(0.0, 0.01, 0.05), seeds=range(50), max_evals: int = 400,
+                        unroll: int = 1) -> dict:
+    """How many evaluations the tuner's local-search strategy needs to come
+    within p of the optimum of a timed space (the use of Section 4's
+    difficulty measure: a walk that reaches a good minimum early makes the
+    space cheap to tune). `times` maps the 6-parameter base tuple to ms (the
+    base sweep); the search runs through conv2d_tune_synthetic with those
+    times as its cost (points without a time fail to compile), once per seed,
+    and the evaluation order it records is replayed against the times. For
+    each p: the median and 90th percentile of the evaluation count at which
+    the best time so far first falls within (1 + p) of the sweep's optimum,
+    and the fraction of seeds that got there within max_evals."""
+    import tempfile
+
+    from . import _binding as B
+    s = B.shape(*shape)
+    best = min(times.values())
+    counts = {p: [] for p in ps}
+    with tempfile.TemporaryDirectory() as tmp:
+        for seed in seeds:
+            path = os.path.join(tmp, f"r{seed}.jsonl")
+            o = B.conv2d_tune_defaults()
+            o.strategy, o.max_evals, o.seed, o.unroll = 1, max_evals, int(seed), unroll
+            o.retime_reps = 0
+            o.results_path = path.encode()
+            B.conv2d_tune_synthetic(s, lambda c: times.get(tuple(c[:6]), B.CONV2D_ECOMPILE), o)
+            order = []
+            with open(path) as fh:
+                for line in fh:
+                    c = tuple(json.loads(line)["config"][:6])
+                    if c not in order:
+                        order.append(c)
+            run = math.inf
+            first = {}
+            for k, c in enumerate(order, 1):
+                run = min(run, times.get(c, math.inf))
+                for p in ps:
+                    if p not in first and run <= (1.0 + p) * best:
+                        first[p] = k
+            for p in ps:
+                counts[p].append(first.get(p))
+
+    def q(v, f):
+        # nearest-rank quantile over every seed; a seed that never got there
+        # counts as beyond the budget (None when the quantile falls there)
+        v = sorted(math.inf if k is None else k for k in v)
+        x = v[min(len(v) - 1, int(f * len(v)))]
+        return None if x == math.inf else x
+
+    out = {"space": len(times), "seeds": len(list(seeds)), "max_evals": max_evals}
+    for p in ps:
+        got = [k for k in counts[p] if k is not None]
+        out[f"p{round(100 * p)}"] = {"reached": round(len(got) / len(counts[p]), 3),
+                                     "median_evals": q(counts[p], 0.5), "p90_evals": q(counts[p], 0.9),
+                                     "per_seed": counts[p]}
+    return out
+
+
+def _current_source_hash() -> str:
+    from . import _binding as B
+    return B.conv2d_kernel_hash()
+
+
+def main(argv=None) -> int:
+    """`python -m paper_2407_11488_amd.analysis effort [--seeds 50] [--max-evals 400]`:
+    the local-search effort over every committed 4096 x 4096 sweep."""
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=("effort",))
+    ap.add_argument("--seeds", type=int, default=50)
+    ap.add_argument("--max-evals", type=int, default=400)
+    ap.add_argument("--filters", type=int, nargs="*", default=[3, 5, 7, 9, 15, 17, 31])
+    a = ap.parse_args(argv)
+    src = _current_source_hash()
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned")
+    for f in a.filters:
+        shape = (4096, 4096, f, f)
+        db = os.path.join(here, results_name("gfx950", shape))
+        times = {c[:6]: r["ms"] for c, r in load(db, shape, src).items()
+                 if r.get("status") == "ok" and r.get("ms", 0) > 0 and c[6] == 1}
+        if not times:
+            continue
+        r = local_search_effort(times, shape, seeds=range(a.seeds), max_evals=a.max_evals)
+        for k in list(r):
+            if isinstance(r[k], dict):
+                r[k].pop("per_seed", None)
+        print(json.dumps({"filter": f, **r}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(main())

@@ -53,3 +53,34 @@ def test_percentile_nearest_rank():
     assert tuning.percentile_nearest_rank(v, 99) == 99
     assert tuning.percentile_nearest_rank([5.0], 99) == 5.0
     assert tuning.percentile_nearest_rank([3, 1, 2], 50) == 2
+
+
+def test_local_search_effort_matches_the_replay():
+    """analysis.local_search_effort runs the tuner's local search (synthetic
+    cost) and reports, per seed, the evaluation at which the best time so far
+    first came within p of the optimum; the oracle's plain replay of the same
+    walk gives the same counts."""
+    import numpy as np
+
+    import paper_2407_11488_amd as C
+    from paper_2407_11488_amd import analysis as A
+    rng = np.random.default_rng(11)
+    shape = (4096, 4096, 17, 17)
+    legal = C.conv2d_space(C.shape(*shape), 1, 0)
+    times = {c[:6]: float(rng.lognormal(0, 0.4)) for c in legal}
+    ps, seeds, budget = (0.0, 0.05), (3, 4, 5), 300
+    got = A.local_search_effort(times, shape, ps=ps, seeds=seeds, max_evals=budget)
+    axes = [list(v) for _, v in space.AXES]
+    best = min(times.values())
+    for p in ps:
+        want = []
+        for seed in seeds:
+            _, order = tuning.local_search({c: times[c[:6]] for c in legal}, legal, axes, budget, seed)
+            run, first = float("inf"), None
+            for k, c in enumerate(order, 1):
+                run = min(run, times[c[:6]])
+                if run <= (1 + p) * best:
+                    first = k
+                    break
+            want.append(first)
+        assert got[f"p{round(100 * p)}"]["per_seed"] == want
