@@ -92,3 +92,20 @@ def test_hotspot_tuner_sweep_and_cache(tmp_path, monkeypatch):
     got = out.cpu().numpy().astype(np.float64)
     assert np.max(np.abs(got - ref)) <= hotspot_bound(temp, power, steps, k)
     hs.close()
+
+
+def test_conv_tuner_local_search_on_gpu(tmp_path):
+    """The local-search strategy with real timings: exactly max_evals points
+    evaluated, all verified, the winner among them and cached."""
+    s = C.shape(*CONV_SHAPE)
+    o = _conv_opts(tmp_path)
+    o.max_configs = 0
+    o.strategy, o.max_evals, o.seed = 1, 30, 5
+    r = C.conv2d_tune(s, o)
+    say(f"local search {CONV_SHAPE}: best {r.best.tuple()} {r.best_ms:.4f} ms, evaluations {r.evaluations}")
+    assert r.evaluations == 30 and r.n_verify_fail == 0 and r.n_launch_fail == 0
+    lines = [json.loads(x) for x in (tmp_path / "results.jsonl").read_text().splitlines() if x.strip()]
+    evaluated = {tuple(x["config"]) for x in lines}
+    assert len(evaluated) == 30 and r.best.tuple() in evaluated
+    got = C.conv2d_cache_lookup(str(tmp_path / "winners.jsonl"), None, s)
+    assert got is not None and got[0].tuple() == r.best.tuple()
