@@ -69,6 +69,10 @@ def _check_direct_kernel():
         _fields_ = [(n, ctypes.c_int) for n in ("block_x", "block_y", "tile_x", "tile_y", "temporal",
                                                  "unroll_t", "sh_power")]
 
+    try:
+        import torch  # noqa: F401  (bind torch's HIP runtime, as the package does)
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB)
     lib.conv2d_last_error.restype = ctypes.c_char_p
     for cfg, vin, vout in (((16, 16, 1, 1, 1, 1, 1), 4, 4), ((64, 1, 8, 8, 0, 0, 1), 1, 2)):
