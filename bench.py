@@ -211,6 +211,7 @@ def main():
     del d_in, d_out
     torch.cuda.empty_cache()
     from paper_2407_11488_amd import workloads
+    line["plain_1024"] = workloads.plain_benchmark()
     if not args.no_batch:
         line["batch"] = workloads.batch_benchmark(reps=20)
     if not args.no_hotspot:

@@ -130,6 +130,40 @@ def batch_benchmark(reps: int = 20, warmup: int = 3, n: int = 64) -> dict:
     return res
 
 
+def plain_benchmark(reps: int = 100, out_hw: int = 1024, f: int = 17) -> dict:
+    """The plain workload: output out_hw^2, filter f x f, input with a zero
+    ring of (f-1)/2 pixels around a uniform interior, the default
+    configuration (no tuning); HIP events over `reps` launches after a
+    warm-up."""
+    torch = _torch()
+    from .api import Plan
+    inp, filt = datagen.conv_problem(out_hw, out_hw, f, f, zero_halo=True)
+    d_in, d_f = torch.from_numpy(inp).cuda(), torch.from_numpy(filt).cuda()
+    out = torch.empty((out_hw, out_hw), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    plan = Plan(out_hw, out_hw, f, f, config=B.conv2d_default_config().tuple())
+    run, sp = B.lib.conv2d_run, st.cuda_stream
+    args = (plan.handle, d_in.data_ptr(), d_f.data_ptr(), out.data_ptr(), sp)
+
+    def once():
+        rc = run(*args)
+        if rc:
+            B.check(rc, "conv2d_run")
+    warm_up(once, st)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        once()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    res = {"workload": f"out {out_hw}x{out_hw}, filter {f}x{f}, input {out_hw + f - 1}^2 with a zero ring, "
+                       "default configuration", "config": list(plan.config), "ms": round(ms, 5),
+           "gflops": round(analysis.flops((out_hw, out_hw, f, f)) / (ms * 1e-3) / 1e9, 1)}
+    plan.close()
+    return res
+
+
 def _trace(rate, duration, seed=datagen.SEED_ARRIVALS):
     t, shapes = datagen.serving_requests(rate, duration, seed=seed)
     k = len(t)
