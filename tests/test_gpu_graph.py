@@ -1,8 +1,11 @@
-"""The plain path under stream capture: conv2d_run recorded into a graph
-(torch.cuda.graph) and replayed several times, with eager work and
-synchronisation between the replays; every replay must equal the eager
-result bit for bit, for a constant-memory filter (a device-to-device copy
-node before the kernel) and a global-pointer filter."""
+"""The plain path under stream capture and under concurrent use.
+
+conv2d_run recorded into a graph (torch.cuda.graph) and replayed several
+times, with eager work and synchronisation between the replays: every replay
+equals the eager result bit for bit, for a constant-memory filter (a
+device-to-device copy node before the kernel) and a global-pointer filter.
+One plan shared by several host threads, each on its own stream: every
+output equals a single-threaded run."""
 import numpy as np
 import pytest
 
@@ -46,4 +49,55 @@ def test_plain_run_captured_and_replayed(cfg):
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint32), want2.cpu().numpy().view(np.uint32))
     del g
+    plan.close()
+
+
+def test_plan_shared_by_threads_on_their_own_streams():
+    """One plan (filter through its pointer) used by four host threads at
+    once, each on its own stream with its own buffers, twenty runs each, the
+    first call of each thread misaligned (the plan's second module is built
+    under its lock): every output equals a single-threaded run bit for bit."""
+    import threading
+    torch = torch_cuda()
+    H, W, fh, fw = 200, 132, 7, 7   # input rows of 138 floats: the main module reads pairs
+    plan = C.Plan(H, W, fh, fw, config=(32, 4, 4, 2, 0, 0, 1))
+    data = [datagen.conv_problem(H, W, fh, fw, seed_in=80 + k, seed_f=90 + k) for k in range(4)]
+    want = []
+    for inp, f in data:
+        o = plan(to_dev(inp), to_dev(f))
+        torch.cuda.synchronize()
+        want.append(o.cpu().numpy().copy())
+    errors = []
+
+    def worker(k):
+        try:
+            s = torch.cuda.Stream()
+            inp, f = data[k]
+            di, df = to_dev(inp), to_dev(f)
+            big_in = torch.zeros(di.numel() + 1, device="cuda")
+            big_in[1:] = di.reshape(-1)
+            big_out = torch.full((H * W + 1,), float("nan"), device="cuda")
+            torch.cuda.synchronize()
+            # first call misaligned by one float, then aligned calls
+            C.conv2d_run(plan.handle, big_in.data_ptr() + 4, df.data_ptr(), big_out.data_ptr() + 4, s.cuda_stream)
+            s.synchronize()
+            if not np.array_equal(big_out[1:].cpu().numpy().view(np.uint32), want[k].reshape(-1).view(np.uint32)):
+                errors.append((k, "misaligned"))
+            out = torch.full((H, W), float("nan"), device="cuda")
+            torch.cuda.synchronize()                   # the fill runs on the default stream
+            for _ in range(20):
+                C.conv2d_run(plan.handle, di.data_ptr(), df.data_ptr(), out.data_ptr(), s.cuda_stream)
+            s.synchronize()
+            if not np.array_equal(out.cpu().numpy().view(np.uint32), want[k].view(np.uint32)):
+                errors.append((k, "aligned"))
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append((k, repr(e)))
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
     plan.close()
