@@ -132,7 +132,7 @@ def cpu_baseline(seconds: float):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only "
+        print(json.dumps({"error": "this library runs on one GPU only; multi-GPU sharding is a design "
                                    "(horizontal bands with a halo exchange), so --gpus must be 1"}))
         return 2
     import torch
