@@ -216,6 +216,10 @@ void conv2d_batch_destroy(conv2d_batch_t batch);
  * side: 1 (up to 384), 2 (385-768), 3 (769-1536), 4 (1537-3072), 5 (larger). */
 #define CONV2D_SIZE_BUCKETS 5
 
+/* The size bucket (1..CONV2D_SIZE_BUCKETS) of an out_h x out_w output
+ * (host only; sides of 0 or less give bucket 1). */
+int conv2d_size_bucket(int out_h, int out_w);
+
 /* Tunes the batched path on a batch: the problems are grouped by filter size
  * (and, with `buckets`, by size bucket too); for each group, its current
  * configuration, the `candidates` fastest points of the tuner's 4096x4096

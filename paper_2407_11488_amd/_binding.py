@@ -341,6 +341,14 @@ lib.conv2d_batch_tune.restype = c_int
 lib.conv2d_batch_tune.argtypes = [c_int, P(Shape), P(BatchTuneOpts), P(BatchTuneResult)]
 
 
+lib.conv2d_size_bucket.restype = c_int
+lib.conv2d_size_bucket.argtypes = [c_int, c_int]
+
+
+def conv2d_size_bucket(out_h: int, out_w: int) -> int:
+    return int(lib.conv2d_size_bucket(int(out_h), int(out_w)))
+
+
 def conv2d_batch_tune_defaults() -> BatchTuneOpts:
     o = BatchTuneOpts()
     lib.conv2d_batch_tune_defaults(ctypes.byref(o))

@@ -594,6 +594,8 @@ struct GroupBench {
 }  // namespace
 }  // namespace conv2d
 
+extern "C" int conv2d_size_bucket(int out_h, int out_w) { return size_bucket(out_h, out_w); }
+
 extern "C" void conv2d_batch_tune_defaults(conv2d_batch_tune_opts* o)
 {
     if (!o) return;

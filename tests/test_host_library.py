@@ -310,3 +310,13 @@ def test_serving_tuner_pick():
     assert pick_serving(t) == t[1]                      # tie on p99 and p50: fewer streams
     assert pick_serving(t, tie_rel=0.0) == t[0]         # no ties: strictly lowest p99
     assert pick_serving(t[3:]) == t[3]
+
+
+def test_size_buckets_follow_the_larger_side():
+    """Bucket edges at larger sides 384, 768, 1536, 3072 (inclusive), and the
+    same rule for the batched path's tuning and its plans."""
+    cases = {(1, 1): 1, (384, 10): 1, (385, 385): 2, (10, 768): 2, (769, 1): 3, (1536, 1536): 3,
+             (1537, 200): 4, (3072, 3072): 4, (3073, 5): 5, (100000, 1): 5, (0, 0): 1}
+    for (h, w), b in cases.items():
+        assert C.conv2d_size_bucket(h, w) == b, (h, w)
+    assert C.conv2d_size_bucket(200, 3000) == C.conv2d_size_bucket(3000, 200) == 4
