@@ -170,6 +170,35 @@ def test_batch_integer_data_bitwise():
     b.close()
 
 
+def test_batch_thousands_of_tiny_problems():
+    """2,000 problems of 1-40 pixels a side with 1x1, 2x3 and 5x5 filters
+    (descriptor and owner tables far larger than a workgroup's tile list,
+    many problems per tile-owner run, images smaller than one tile), integer
+    data: every output equals the oracle bit for bit."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(17)
+    filters = [(1, 1), (2, 3), (5, 5)]
+    shapes = []
+    for k in range(2000):
+        fh, fw = filters[k % 3]
+        shapes.append((int(rng.integers(1, 41)), int(rng.integers(1, 41)), fh, fw))
+    probs = [datagen.conv_problem(*s, kind="int", seed_in=5000 + k, seed_f=9000 + k) for k, s in enumerate(shapes)]
+    b = C.Batch(shapes)
+    say(f"tiny batch: {b.info['n_groups']} groups, {b.info['total_tiles']} tiles")
+    ins = [torch.from_numpy(i).cuda() for i, _ in probs]
+    fs = [torch.from_numpy(f).cuda() for _, f in probs]
+    outs = [torch.full((H, W), float("nan"), device="cuda") for (H, W, _, _) in shapes]
+    b(ins, fs, outs)
+    torch.cuda.synchronize()
+    bad = []
+    for k, (inp, f) in enumerate(probs):
+        ref, _ = oracle.conv2d_f64(inp, f)
+        if not np.array_equal(outs[k].cpu().numpy().astype(np.float64), ref):
+            bad.append(k)
+    assert not bad, bad[:10]
+    b.close()
+
+
 def test_batch_errors():
     torch = torch_cuda()
     with pytest.raises(C.Conv2dError):
