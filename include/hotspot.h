@@ -88,10 +88,13 @@ int hotspot_compile(const hotspot_config *cfg, char *path_out, int path_cap);
 
 /* Plans a grid: cfg, else the tuned winner of the hotspot winners cache for
  * this grid size (tuned/hotspot_winners.jsonl beside the library, or
- * $HOTSPOT_WINNERS), else the default. Compiles and loads the kernel. */
+ * $HOTSPOT_WINNERS), else the winner for another grid that is legal here
+ * (4096 x 4096 first, else the most recent), else the default. Compiles and
+ * loads the kernel. */
 int hotspot_plan(hotspot_plan_t *plan, hotspot_shape s, const hotspot_config *cfg);
 
-/* The plan's configuration; *tuned = 1 when it came from the winners cache. */
+/* The plan's configuration; *tuned = 1 when it is this grid's winner, 2
+ * when it is another grid's, 0 otherwise (given or default). */
 int hotspot_plan_config(hotspot_plan_t plan, hotspot_config *cfg, int *tuned);
 
 /* d_out = the grid after `steps` (>= 0) steps from d_temp, on `stream`:

@@ -153,7 +153,7 @@ class Hotspot:
         self.shape = B.hotspot_shape(rows, cols)
         self.handle = B.hotspot_plan(self.shape, config)
         self.config, tuned = B.hotspot_plan_config(self.handle)
-        self.source = "given" if config is not None else ("tuned" if tuned else "default")
+        self.source = "given" if config is not None else {1: "tuned", 2: "tuned-other-grid"}.get(tuned, "default")
         self._work = None
 
     def __call__(self, temp, power, steps, coeffs, out=None, stream=None):

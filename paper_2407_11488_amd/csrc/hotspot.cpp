@@ -245,6 +245,39 @@ int hs_cache_lookup(const std::string& path, const std::string& arch, const hots
     return CONV2D_OK;
 }
 
+// The winner for another grid, for a grid without an entry of its own: the
+// 4096 x 4096 entry first, else the most recent entry (of the current kernel
+// source before older ones) whose configuration is legal for grid s.
+int hs_cache_lookup_other(const std::string& path, const std::string& arch, const hotspot_shape& s, int lds_limit,
+                          hotspot_config* c)
+{
+    const hotspot_shape big{4096, 4096};
+    hotspot_config cand{};
+    if (hs_cache_lookup(path, arch, big, &cand, nullptr) == CONV2D_OK &&
+        hotspot_config_check(s, &cand, lds_limit) == CONV2D_OK) {
+        *c = cand;
+        return CONV2D_OK;
+    }
+    std::ifstream f(path);
+    if (!f) return fail(CONV2D_ENOTUNED, "no hotspot winners cache at " + path);
+    const std::string src = hex64(hs_source_hash());
+    bool have_cur = false, have_old = false;
+    hotspot_config cur{}, old{};
+    std::string line;
+    while (std::getline(f, line)) {
+        JsonObj o;
+        if (!json_parse_line(line, &o) || o.str["arch"] != arch) continue;
+        hotspot_config cc;
+        if (!json_hs_config(o, &cc) || hotspot_config_check(s, &cc, lds_limit) != CONV2D_OK) continue;
+        if (o.str["src"] == src) { cur = cc; have_cur = true; }
+        else { old = cc; have_old = true; }
+    }
+    clear_error();
+    if (!have_cur && !have_old) return fail(CONV2D_ENOTUNED, "no legal hotspot winner for this grid");
+    *c = have_cur ? cur : old;
+    return CONV2D_OK;
+}
+
 std::string record_line(const std::string& arch, const hotspot_shape& s, int steps, const RecordT<hotspot_config>& r,
                         double gflops)
 {
@@ -592,6 +625,8 @@ extern "C" int hotspot_plan(hotspot_plan_t* out, hotspot_shape s, const hotspot_
         if (hs_cache_lookup(wp, dev.arch, s, &p->cfg, nullptr) == CONV2D_OK &&
             hotspot_config_check(s, &p->cfg, dev.lds_limit) == CONV2D_OK)
             p->tuned = 1;
+        else if (hs_cache_lookup_other(wp, dev.arch, s, dev.lds_limit, &p->cfg) == CONV2D_OK)
+            p->tuned = 2;
         else
             hotspot_default_config(&p->cfg);
         clear_error();

@@ -122,6 +122,32 @@ def test_edge_cases():
     plan.close()
 
 
+def test_ungridded_plan_takes_another_grids_winner(tmp_path, monkeypatch):
+    """A grid with no winners entry of its own takes the 4096 x 4096 winner
+    (source "tuned-other-grid"); with no entry at all it takes the default;
+    either way the result stays within the FP32 bound of the oracle."""
+    import json
+    torch = torch_cuda()
+    cfg = (64, 4, 2, 4, 4, 1, 1)
+    full = tmp_path / "hs_winners.jsonl"
+    full.write_text(json.dumps({"arch": "gfx950", "src": "0000000000000000", "shape": [4096, 4096],
+                                "config": list(cfg), "ms": 1.0}) + "\n")
+    empty = tmp_path / "none.jsonl"
+    empty.write_text("")
+    rows, cols = 300, 200
+    temp, power, k = datagen.hotspot_problem(rows, cols)
+    ref = oracle.hotspot_f64(temp, power, 9, *k)
+    for path, want in ((full, ("tuned-other-grid", cfg)), (empty, ("default", C.hotspot_default_config().tuple()))):
+        monkeypatch.setenv("HOTSPOT_WINNERS", str(path))
+        hs = C.Hotspot(rows, cols)
+        say(f"hotspot {rows}x{cols} with {path.name}: {hs.source} {hs.config}")
+        assert (hs.source, tuple(hs.config)) == want
+        out = hs(torch.from_numpy(temp).cuda(), torch.from_numpy(power).cuda(), 9, k)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(out.cpu().numpy().astype(np.float64) - ref)) <= bound(temp, power, 9, k)
+        hs.close()
+
+
 def test_errors_are_reported_not_faulted():
     torch = torch_cuda()
     s = C.hotspot_shape(64, 64)
