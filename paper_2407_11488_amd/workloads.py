@@ -23,9 +23,10 @@ default configuration.
 plain (bench.py only): the 1024 x 1024 / 17 x 17 workload with a zero input
 ring in the default configuration.
 
-Each prints one JSON line. Every timed loop follows at least 25 ms of warm-up
-work (the GPU leaves its set-up at a lower clock) and enqueues with its
-arguments marshalled beforehand, so that events time the GPU, not Python.
+Each prints one JSON line. The batch, hotspot and plain loops follow at
+least 25 ms of warm-up work (the GPU leaves its set-up at a lower clock) and
+enqueue with their arguments marshalled beforehand, so that events time the
+GPU, not Python; the serving runs follow the capacity probes.
 The server's stream count and batch cap default to the tuned pair in
 tuned/serve_params.json (tune.py --serving), else 4 and 64.
 """
