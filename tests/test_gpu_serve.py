@@ -87,6 +87,34 @@ def test_results_same_alone_and_in_the_mix(serial):
         C.conv2d_serve_free(outs)
 
 
+def test_mixed_size_buckets_same_alone_and_in_the_mix():
+    """Requests spanning every size bucket (sides 200 to 3,500, all four
+    filter sizes), most arriving together: the server gives each its bucket's
+    configuration and launches one kernel per filter size and configuration
+    of a batch; every output equals the plain path's on the same data, bit
+    for bit (the plain path is pinned against the oracle elsewhere)."""
+    sides = [200, 450, 900, 1700, 3500, 300, 700, 1200, 2500, 3100, 380, 1000]
+    fs = [3, 5, 9, 17, 3, 17, 9, 5, 3, 9, 17, 5]
+    shapes = [(s, s + (k % 3), f, f) for k, (s, f) in enumerate(zip(sides, fs))]
+    assert {C.conv2d_size_bucket(h, w) for (h, w, _, _) in shapes} == {1, 2, 3, 4, 5}
+    t = np.zeros(len(shapes))
+    t[8:] = [1e-4, 2e-4, 3e-4, 4e-4]
+    reqs = C.requests_array(t, shapes, [7000 + k for k in range(len(shapes))],
+                            [8000 + k for k in range(len(shapes))])
+    o = C.conv2d_serve_defaults()
+    o.streams, o.max_batch = 2, 8
+    rep, lat, outs = C.conv2d_serve(reqs, o, keep_outputs=True)
+    try:
+        say(f"mixed buckets: {rep.as_dict()}")
+        assert rep.n_requests == len(shapes) and rep.n_batches < len(shapes)
+        for k, (H, W, fh, fw) in enumerate(shapes):
+            got = _copy_out(outs[k], H, W).cpu().numpy()
+            alone = _plain(shapes[k], 7000 + k, 8000 + k).cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), alone.view(np.uint32)), k
+    finally:
+        C.conv2d_serve_free(outs)
+
+
 def test_budget_admission_bounds_memory():
     reqs, shapes = small_trace(n=40, rate=1e6, seed=21, lo=200, hi=400)
     need = [4 * ((H + fh - 1) * (W + fw - 1) + fh * fw + H * W) + 3 * 256 for (H, W, fh, fw) in shapes]
