@@ -83,8 +83,10 @@ int conv2d_version(void);
 /* Thread-local text of the last non-zero return on this thread ("" if none). */
 const char *conv2d_last_error(void);
 
-/* Hex hash of the tunable kernel source built into this library (keys the
- * winners cache and the code-object cache). Static storage, never NULL. */
+/* Hex hash of the tunable kernel source built into this library, taken over
+ * its code with comments and blank runs removed (keys the winners cache and
+ * the tuner's results; editing comments keeps them valid). Static storage,
+ * never NULL. */
 const char *conv2d_kernel_hash(void);
 
 /* The untuned default configuration: the textbook 16x16-thread tiled kernel,

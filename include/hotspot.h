@@ -61,6 +61,11 @@ typedef struct hotspot_plan_s *hotspot_plan_t;
 
 /* ------------------------------------------------------------ host-only helpers */
 
+/* Hex hash of the hotspot kernel source built into this library (its code
+ * without comments and blank runs; keys the hotspot winners cache and
+ * results). Static storage, never NULL. */
+const char *hotspot_kernel_hash(void);
+
 /* (32, 8, 1, 1, 1, 1, 1): one cell per thread, one step per launch. */
 void hotspot_default_config(hotspot_config *cfg);
 

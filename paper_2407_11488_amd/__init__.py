@@ -28,5 +28,5 @@ from ._binding import (HotspotCoeffs, HotspotConfig, HotspotShape, HotspotTuneOp
                        HotspotTuneResult, hotspot_coeffs, hotspot_compile, hotspot_config,
                        hotspot_config_check, hotspot_default_config, hotspot_destroy, hotspot_lds_bytes,
                        hotspot_plan, hotspot_plan_config, hotspot_reference, hotspot_run, hotspot_shape,
-                       hotspot_space, hotspot_tune, hotspot_tune_defaults)
+                       hotspot_kernel_hash, hotspot_space, hotspot_tune, hotspot_tune_defaults)
 from .api import Batch, Hotspot, Plan, conv2d, reference, reference_hotspot  # noqa: F401

@@ -566,6 +566,14 @@ def hotspot_reference(s: HotspotShape, d_temp: int, d_power: int, d_out: int, d_
     check(lib.hotspot_reference(s, d_temp, d_power, d_out, d_work, int(steps), k, stream), "hotspot_reference")
 
 
+lib.hotspot_kernel_hash.restype = c_char_p
+lib.hotspot_kernel_hash.argtypes = []
+
+
+def hotspot_kernel_hash() -> str:
+    return lib.hotspot_kernel_hash().decode()
+
+
 def hotspot_tune_defaults() -> HotspotTuneOpts:
     o = HotspotTuneOpts()
     lib.hotspot_tune_defaults(ctypes.byref(o))

@@ -49,6 +49,47 @@ uint64_t fnv1a(const void* data, size_t n, uint64_t h)
 
 uint64_t fnv1a(const std::string& s, uint64_t h) { return fnv1a(s.data(), s.size(), h); }
 
+std::string code_text(const std::string& s)
+{
+    std::string out;
+    out.reserve(s.size());
+    const size_t n = s.size();
+    auto space = [&] {
+        if (!out.empty() && out.back() != ' ' && out.back() != '\n') out += ' ';
+    };
+    size_t i = 0;
+    while (i < n) {
+        const char c = s[i];
+        if (c == '/' && i + 1 < n && s[i + 1] == '/') {           // line comment: up to the newline
+            while (i < n && s[i] != '\n') ++i;
+        } else if (c == '/' && i + 1 < n && s[i + 1] == '*') {    // block comment: one space
+            const size_t e = s.find("*/", i + 2);
+            i = e == std::string::npos ? n : e + 2;
+            space();
+        } else if (c == '"' || c == '\'') {                       // literal, copied as is
+            out += c;
+            ++i;
+            while (i < n && s[i] != c) {
+                if (s[i] == '\\' && i + 1 < n) out += s[i++];
+                out += s[i++];
+            }
+            if (i < n) out += s[i++];
+        } else if (c == '\n') {                                   // newlines matter (directives)
+            while (!out.empty() && out.back() == ' ') out.pop_back();
+            if (!out.empty() && out.back() != '\n') out += '\n';
+            ++i;
+        } else if (c == ' ' || c == '\t' || c == '\r' || c == '\f' || c == '\v') {
+            space();
+            ++i;
+        } else {
+            out += c;
+            ++i;
+        }
+    }
+    while (!out.empty() && (out.back() == ' ' || out.back() == '\n')) out.pop_back();
+    return out;
+}
+
 std::string hex64(uint64_t v)
 {
     char b[17];

@@ -36,7 +36,7 @@ const std::string& hs_source()
 
 uint64_t hs_source_hash()
 {
-    static const uint64_t h = fnv1a(hs_source());
+    static const uint64_t h = fnv1a(code_text(hs_source()));
     return h;
 }
 
@@ -602,6 +602,12 @@ extern "C" int hotspot_compile(const hotspot_config* cfg, char* path_out, int pa
         path_out[path_cap - 1] = '\0';
     }
     return CONV2D_OK;
+}
+
+extern "C" const char* hotspot_kernel_hash(void)
+{
+    static const std::string h = hex64(hs_source_hash());
+    return h.c_str();
 }
 
 extern "C" int hotspot_plan(hotspot_plan_t* out, hotspot_shape s, const hotspot_config* cfg)

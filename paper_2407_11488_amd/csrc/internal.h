@@ -28,6 +28,11 @@ int hip_fail(hipError_t e, const char* what);
 // ---------------------------------------------------------------- misc
 uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull);
 uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull);
+// A kernel source with its comments removed and its blanks collapsed (one
+// space inside a line, no empty lines; literals kept as they are): the text
+// whose hash keys tuned results, so that editing comments or layout keeps
+// them valid while any change to the code does not.
+std::string code_text(const std::string& source);
 std::string hex64(uint64_t v);
 std::string env_str(const char* name, const char* dflt = "");
 // Directory that holds this shared library.

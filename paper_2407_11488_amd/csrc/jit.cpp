@@ -24,7 +24,7 @@ const std::string& direct_source()
 
 uint64_t direct_source_hash()
 {
-    static const uint64_t h = fnv1a(direct_source());
+    static const uint64_t h = fnv1a(code_text(direct_source()));
     return h;
 }
 
