@@ -25,7 +25,7 @@
 //   CONV_VOUT          output vector width 1/2/4 (row pitch and base aligned)
 //   CONV_NAME          kernel symbol (one per configuration, so that profiles
 //                      tell configurations apart); default conv2d_direct
-//   CONV_BATCH         1: build the persistent batched kernel (many images of
+//   CONV_BATCH         1: build the batched kernel (many images of
 //                      one filter size, described in device memory) instead
 //
 // Design (MI355X):
@@ -291,10 +291,11 @@ static __device__ __forceinline__ const ConvDesc* tile_desc(const ConvDesc* __re
     return descs + __builtin_amdgcn_readfirstlane((int)owner[t]);
 }
 
-// Many images with the same filter size: a persistent grid (at least 8
-// workgroups) walks the group's tile list. The tiles of XCD x (= workgroup id
-// mod 8) form one contiguous range, shared out by stride among that XCD's
-// workgroups; owner[t] names the problem of tile t.
+// Many images with the same filter size: a grid of at least 8 workgroups
+// walks the group's tile list (the library launches one workgroup per tile;
+// a smaller grid gives each workgroup several). The tiles of XCD x (=
+// workgroup id mod 8) form one contiguous range, shared out by stride among
+// that XCD's workgroups; owner[t] names the problem of tile t.
 using G1 = Geo<CONV_FH, CONV_FW, CONV_BX, CONV_BY, CONV_TX, CONV_TY, CONV_USE_LDS, CONV_UNROLL, CONV_VIN, CONV_VOUT>;
 extern "C" __global__ void __launch_bounds__(G1::NT)
 CONV_NAME(const ConvDesc* __restrict__ descs, const unsigned short* __restrict__ owner, int total_tiles)
