@@ -84,3 +84,52 @@ def test_local_search_effort_matches_the_replay():
                     break
             want.append(first)
         assert got[f"p{round(100 * p)}"]["per_seed"] == want
+
+
+def test_results_analysis_matches_the_statistics_oracle(tmp_path):
+    """The product's results-database analysis (NEXT-1: impact, percentiles,
+    application efficiency, performance portability and the most portable
+    configuration over shapes) against the statistics oracle computed
+    directly from the same synthetic times; failed points are ignored."""
+    import json
+
+    import numpy as np
+
+    from paper_2407_11488_amd import analysis as A
+    rng = np.random.default_rng(5)
+    configs = [(bx, by, tx, 1, 0, 0, 1) for bx in (16, 32, 64, 128) for by in (1, 2, 4) for tx in (1, 2, 4, 8)]
+    shapes = [(512, 512, 3, 3), (512, 512, 9, 9), (512, 512, 17, 17)]
+    dbs, times = {}, {}
+    for s in shapes:
+        db = tmp_path / f"r_{s[2]}.jsonl"
+        t = {c: float(rng.lognormal(0, 0.5)) for c in configs}
+        failed = set(configs[3::11])
+        with open(db, "w") as fh:
+            for c in configs:
+                st = "verify" if c in failed else "ok"
+                fh.write(json.dumps({"arch": "gfx950", "src": "x", "shape": list(s), "config": list(c),
+                                     "status": st, "ms": t[c] if st == "ok" else 0.0}) + "\n")
+        dbs[s] = str(db)
+        times[s] = {c: v for c, v in t.items() if c not in failed}
+    for s in shapes:
+        perf = {c: tuning.gflops(*s, ms * 1e-3) for c, ms in times[s].items()}
+        assert A.impact(dbs[s], s) == pytest.approx(tuning.tuning_impact(list(perf.values())), rel=1e-12)
+        best = max(perf.values())
+        pc = A.percentiles(dbs[s], s)
+        for q in (10, 25, 50, 75, 90):
+            assert pc[f"p{q}"] == pytest.approx(tuning.percentile_nearest_rank(list(perf.values()), q) / best,
+                                                abs=5e-5)
+        c0 = next(iter(times[s]))
+        e = A.efficiency_of(dbs[s], s, c0)["efficiency"]
+        assert e == pytest.approx(tuning.efficiency(perf[c0], list(perf.values())), abs=5e-5)
+    cfg, row = A.most_portable(dbs)
+    common = set.intersection(*(set(times[s]) for s in shapes))
+
+    def pp(c):
+        effs = []
+        for s in shapes:
+            perf = {k: tuning.gflops(*s, ms * 1e-3) for k, ms in times[s].items()}
+            effs.append(tuning.efficiency(perf[c], list(perf.values())))
+        return tuning.performance_portability(effs)
+    want = max(sorted(common), key=pp)
+    assert cfg == want and row["pp"] == pytest.approx(pp(want), rel=1e-12)
