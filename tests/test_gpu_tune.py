@@ -109,3 +109,16 @@ def test_conv_tuner_local_search_on_gpu(tmp_path):
     assert len(evaluated) == 30 and r.best.tuple() in evaluated
     got = C.conv2d_cache_lookup(str(tmp_path / "winners.jsonl"), None, s)
     assert got is not None and got[0].tuple() == r.best.tuple()
+
+
+def test_benchmark_one_configuration():
+    """conv2d_benchmark times one configuration the tuner's way: a verified
+    launch, then timed launches; the median is at least the minimum, both
+    positive; a configuration illegal for the shape is rejected."""
+    s = C.shape(*CONV_SHAPE)
+    cfg = (64, 2, 4, 4, 1, 0, 1)
+    med, mn = C.conv2d_benchmark(s, cfg, 1, 7, 1)
+    say(f"benchmark {cfg}: median {med:.4f} ms, min {mn:.4f} ms")
+    assert 0 < mn <= med
+    with pytest.raises(C.Conv2dError):
+        C.conv2d_benchmark(C.shape(64, 64, 63, 63), (128, 8, 8, 8, 1, 0, 1), 1, 3, 0)   # LDS too large
