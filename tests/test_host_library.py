@@ -84,6 +84,34 @@ def test_compiled_code_is_plain_fp32_fma_without_spills(cfg):
     assert n["private_segment_fixed_size"] == 0 and n["vgpr_spill_count"] == 0
 
 
+def test_batched_kernels_of_the_cached_choices_compile_without_spills():
+    """The batched kernel of every configuration the batched path and the
+    server take from the committed winners cache (whole-batch and size-bucket
+    entries; filter through its pointer, rolled row loop as the library
+    builds it when needed): no packed FP32, no scratch, no VGPR spills."""
+    import json as _json
+    wp = os.path.join(ROOT, "paper_2407_11488_amd", "tuned", "winners.jsonl")
+    seen = set()
+    for line in open(wp):
+        r = _json.loads(line)
+        sh, c = r["shape"], tuple(r["config"])
+        if sh[0] != 0 or r.get("arch") != "gfx950":
+            continue
+        for unroll in sorted({c[6], 1}):
+            cfg = c[:5] + (0, unroll)
+            key = (sh[2], sh[3], cfg)
+            if key in seen:
+                continue
+            seen.add(key)
+            path = C.conv2d_compile_batch(C.shape(4096, 4096, sh[2], sh[3]), cfg)
+            isa = subprocess.run([OBJDUMP, "-d", path], capture_output=True, text=True).stdout
+            assert "v_pk_" not in isa, key
+            n = _notes(path)
+            if unroll == 1:
+                assert n["private_segment_fixed_size"] == 0 and n["vgpr_spill_count"] == 0, key
+    assert len(seen) >= 8
+
+
 def xcd_remap(i, n):
     q, rem = n >> 3, n & 7
     x, k = i & 7, i >> 3
