@@ -22,3 +22,19 @@ def test_kernel_check_then_package_import_in_one_process():
                        timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.startswith("ok ")
+
+
+def test_package_refuses_to_load_without_the_hip_library(tmp_path):
+    """No CPU fallback: the package without its built HIP library raises on
+    import, naming the missing library and how to build it."""
+    import shutil
+    pkg = os.path.join(ROOT, "paper_2407_11488_amd")
+    dst = tmp_path / "paper_2407_11488_amd"
+    dst.mkdir()
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            shutil.copy(os.path.join(pkg, name), dst / name)
+    code = "import sys; sys.path.insert(0, {!r}); import paper_2407_11488_amd".format(str(tmp_path))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=str(tmp_path))
+    assert r.returncode != 0
+    assert "libconv2d.so is missing" in r.stderr
