@@ -128,7 +128,7 @@ def test_batch_edge_cases():
 
 
 def test_batch_many_filter_sizes():
-    """Eleven filter sizes (eleven persistent kernels as graph branches),
+    """Eleven filter sizes (eleven kernels as graph branches),
     uneven images, integer data: bitwise equal to the oracle on every replay."""
     torch = torch_cuda()
     filters = [(1, 1), (3, 3), (5, 5), (7, 7), (9, 9), (11, 11), (2, 6), (6, 2), (17, 17), (31, 31), (4, 4)]
