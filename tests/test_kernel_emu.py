@@ -132,8 +132,10 @@ def build_batch(cfg, fh, fw):
 
 @pytest.mark.parametrize("fh,fw", [(3, 3), (5, 2)])
 def test_emulated_batch_kernel_exact(fh, fw, tmp_path):
-    """The persistent kernel over uneven images: every output of every image
-    written once and exact, for grids that are and are not multiples of 8."""
+    """The batched kernel over uneven images on grids smaller than its tile
+    count (each workgroup striding over several tiles): every output of every
+    image written once and exact, for grids that are and are not multiples
+    of 8."""
     sizes = [(37, 45), (5, 130), (64, 64), (1, 1), (19, 7)]
     probs = []
     for k, (H, W) in enumerate(sizes):
