@@ -139,6 +139,8 @@ def most_portable(dbs: dict):
 # ---------------------------------------------------------------- tuning difficulty
 
 SPACE_AXES = ((16, 32, 64, 128), (1, 2, 4, 8, 16), (1, 2, 4, 8), (1, 2, 4, 8), (0, 1), (0, 1))
+# The hotspot space (block_x, block_y, tile_x, tile_y, temporal, unroll_t, sh_power).
+HOTSPOT_AXES = ((16, 32, 64, 128, 256), (1, 2, 4, 8, 16), (1, 2, 4), (1, 2, 4), (1, 2, 3, 4, 6, 8), (0, 1), (0, 1))
 
 
 def fitness_flow_graph(times: dict, axes=SPACE_AXES):
@@ -267,16 +269,53 @@ def _current_source_hash() -> str:
     return B.conv2d_kernel_hash()
 
 
+def hotspot_sweep_times(db: str, grid, steps: int = 60, src: str | None = None) -> dict:
+    """Times (ms) of the verified points of a hotspot sweep (the last record
+    of each configuration), keyed by the 7-parameter tuple."""
+    out = {}
+    if not os.path.exists(db):
+        return out
+    with open(db) as fh:
+        for line in fh:
+            try:
+                r = json.loads(line)
+            except json.JSONDecodeError:
+                continue
+            if tuple(r.get("shape", ())) != tuple(grid) or r.get("steps") != steps or (src and r.get("src") != src):
+                continue
+            c = tuple(int(v) for v in r["config"])
+            if r.get("status") == "ok" and r.get("ms", 0) > 0:
+                out[c] = r["ms"]
+            else:
+                out.pop(c, None)
+    return out
+
+
 def main(argv=None) -> int:
     """`python -m paper_2407_11488_amd.analysis effort [--seeds 50] [--max-evals 400]`:
-    the local-search effort over every committed 4096 x 4096 sweep."""
+    the local-search effort over every committed 4096 x 4096 sweep;
+    `... analysis hotspot-difficulty`: Eq. 1's centrality over the committed
+    hotspot sweeps."""
     import argparse
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=("effort",))
+    ap.add_argument("what", choices=("effort", "hotspot-difficulty"))
     ap.add_argument("--seeds", type=int, default=50)
     ap.add_argument("--max-evals", type=int, default=400)
     ap.add_argument("--filters", type=int, nargs="*", default=[3, 5, 7, 9, 15, 17, 31])
     a = ap.parse_args(argv)
+    if a.what == "hotspot-difficulty":
+        from . import _binding as B
+        hsrc = B.hotspot_kernel_hash()
+        here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned")
+        for n in (2048, 4096, 8192):
+            db = os.path.join(here, f"hotspot_results_gfx950_{n}x{n}_s60.jsonl")
+            times = hotspot_sweep_times(db, (n, n), 60, hsrc)
+            if not times:
+                continue
+            pc = proportion_of_centrality(times, axes=HOTSPOT_AXES)
+            print(json.dumps({"grid": [n, n], "points": len(times),
+                              "C": {f"{round(100 * p)}%": round(v, 3) for p, v in pc.items()}}), flush=True)
+        return 0
     src = _current_source_hash()
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned")
     for f in a.filters:

@@ -74,3 +74,29 @@ def test_committed_sweep_difficulty():
     got = A.proportion_of_centrality(times, ps)
     for p in ps:
         assert got[p] == pytest.approx(ot.proportion_of_centrality(times, AXES6, p), abs=1e-9)
+
+
+def test_hotspot_sweep_loader_and_axes(tmp_path):
+    """hotspot_sweep_times keeps the last verified record of each
+    configuration of one grid and step count; every committed hotspot point
+    lies on the hotspot axes, so the fitness flow graph covers it."""
+    import json as _json
+    import os as _os
+    db = tmp_path / "h.jsonl"
+    rows = [
+        {"shape": [64, 64], "steps": 60, "config": [32, 8, 1, 1, 1, 1, 1], "status": "ok", "ms": 2.0},
+        {"shape": [64, 64], "steps": 60, "config": [32, 8, 1, 1, 1, 1, 1], "status": "ok", "ms": 1.5},
+        {"shape": [64, 64], "steps": 60, "config": [64, 8, 1, 1, 1, 1, 1], "status": "verify", "ms": 0.0},
+        {"shape": [64, 64], "steps": 30, "config": [16, 8, 1, 1, 1, 1, 1], "status": "ok", "ms": 1.0},
+        {"shape": [32, 32], "steps": 60, "config": [16, 8, 1, 1, 1, 1, 1], "status": "ok", "ms": 1.0},
+    ]
+    db.write_text("".join(_json.dumps(r) + "\n" for r in rows) + "{broken\n")
+    assert A.hotspot_sweep_times(str(db), (64, 64), 60) == {(32, 8, 1, 1, 1, 1, 1): 1.5}
+    here = _os.path.join(_os.path.dirname(_os.path.dirname(_os.path.abspath(__file__))), "paper_2407_11488_amd",
+                         "tuned", "hotspot_results_gfx950_4096x4096_s60.jsonl")
+    times = A.hotspot_sweep_times(here, (4096, 4096), 60)
+    assert len(times) == 2040
+    for c in times:
+        assert all(v in axis for v, axis in zip(c, A.HOTSPOT_AXES)), c
+    nodes, out = A.fitness_flow_graph(times, A.HOTSPOT_AXES)
+    assert any(out) and not out[nodes.index(min(times, key=times.get))]   # the optimum is a sink
