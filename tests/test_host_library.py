@@ -348,3 +348,27 @@ def test_size_buckets_follow_the_larger_side():
     for (h, w), b in cases.items():
         assert C.conv2d_size_bucket(h, w) == b, (h, w)
     assert C.conv2d_size_bucket(200, 3000) == C.conv2d_size_bucket(3000, 200) == 4
+
+
+def test_bench_traffic_record_matches_only_its_kernel():
+    """bench.py reports the committed rocprofv3 traffic only for the kernel
+    source and configuration it was measured on (else null): the record
+    matches the committed 4096x4096 / 17x17 winner of the current source."""
+    import sys as _sys
+    _sys.path.insert(0, ROOT)
+    import bench
+    rec = json.load(open(os.path.join(ROOT, "profiles", "conv2d_direct_4096x4096_f17_traffic.json")))
+
+    class Plan:
+        config = tuple(rec["config"])
+    assert rec["kernel_hash"] == C.conv2d_kernel_hash()
+    got, src = bench.measured_traffic(C, Plan())
+    assert got == rec["traffic_bytes_per_launch"] and src.endswith("_traffic.json")
+    assert 1.0 <= got / rec["algorithmic_bytes_per_launch"] < 1.1
+
+    class Other:
+        config = (16, 16, 1, 1, 1, 1, 1)
+    assert bench.measured_traffic(C, Other()) == (None, None)
+    win = C.conv2d_cache_lookup(os.path.join(ROOT, "paper_2407_11488_amd", "tuned", "winners.jsonl"), "gfx950",
+                                C.shape(4096, 4096, 17, 17))
+    assert win is not None and win[0].tuple() == tuple(rec["config"])
