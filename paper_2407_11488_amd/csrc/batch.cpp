@@ -107,13 +107,22 @@ static int capture(conv2d_batch_s* b)
     hipStream_t root = streams[0];
     hipError_t e = hipStreamBeginCapture(root, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipStreamBeginCapture"); }
-    hipEventRecord(events[0], root);
+    e = hipEventRecord(events[0], root);
+    if (e != hipSuccess) rc = hip_fail(e, "hipEventRecord (capture fork)");
     for (size_t g = 0; g < b->groups.size() && rc == CONV2D_OK; ++g) {
         hipStream_t st = streams[g + 1];
-        hipStreamWaitEvent(st, events[0], 0);
+        if ((e = hipStreamWaitEvent(st, events[0], 0)) != hipSuccess) {
+            rc = hip_fail(e, "hipStreamWaitEvent (capture fork)");
+            break;
+        }
         rc = launch_group(b->groups[g], st);
-        hipEventRecord(events[g + 1], st);
-        hipStreamWaitEvent(root, events[g + 1], 0);
+        // The branch is joined back to the root stream even after a failed
+        // launch, so that the capture can end.
+        if ((e = hipEventRecord(events[g + 1], st)) != hipSuccess ||
+            (e = hipStreamWaitEvent(root, events[g + 1], 0)) != hipSuccess) {
+            if (rc == CONV2D_OK) rc = hip_fail(e, "capture join");
+            break;
+        }
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(root, &graph);
