@@ -79,12 +79,15 @@ def conv2d(inp, filt, config=None, out=None, stream=None):
 def reference(inp, filt, out=None, stream=None):
     """The library's plain reference kernel (one thread per output)."""
     torch = _torch()
-    fh, fw = filt.shape
-    H, W = inp.shape[0] - fh + 1, inp.shape[1] - fw + 1
     _check_tensor(inp, "inp")
     _check_tensor(filt, "filt")
+    if inp.dim() != 2 or filt.dim() != 2:
+        raise ValueError("inp and filt must be 2-D")
+    fh, fw = filt.shape
+    H, W = inp.shape[0] - fh + 1, inp.shape[1] - fw + 1
     if out is None:
         out = torch.empty((H, W), dtype=torch.float32, device=inp.device)
+    _check_tensor(out, "out", (H, W))
     B.conv2d_reference(B.shape(H, W, fh, fw), inp.data_ptr(), filt.data_ptr(), out.data_ptr(), _stream(stream))
     return out
 
@@ -157,7 +160,9 @@ class Hotspot:
         self._work = None
 
     def __call__(self, temp, power, steps, coeffs, out=None, stream=None):
-        """The grid after `steps` steps; coeffs = (cc, gx, gy, gz, t_amb)."""
+        """The grid after `steps` steps; coeffs = (cc, gx, gy, gz, t_amb).
+        Calls of one Hotspot object share its work grid: calls on different
+        streams must not overlap."""
         torch = _torch()
         shp = (self.shape.rows, self.shape.cols)
         _check_tensor(temp, "temp", shp)
@@ -189,9 +194,14 @@ class Hotspot:
 def reference_hotspot(temp, power, steps, coeffs, out=None, stream=None):
     """The library's one-step-per-launch hotspot reference."""
     torch = _torch()
+    _check_tensor(temp, "temp")
+    if temp.dim() != 2:
+        raise ValueError("temp must be 2-D")
     rows, cols = temp.shape
+    _check_tensor(power, "power", (rows, cols))
     if out is None:
         out = torch.empty((rows, cols), dtype=torch.float32, device=temp.device)
+    _check_tensor(out, "out", (rows, cols))
     # torch's caching allocator keeps the work buffer's memory for this
     # stream until the stream has passed the launches
     work = torch.empty((rows, cols), dtype=torch.float32, device=temp.device) if steps > 1 else None

@@ -178,3 +178,25 @@ def test_errors_are_reported_not_faulted():
         C.hotspot_plan(s, (16, 1, 1, 1, 1, 1, 1))    # 16 threads: below the minimum
     with pytest.raises(C.Conv2dError):
         C.hotspot_plan(C.hotspot_shape(0, 5))
+
+
+def test_reference_helpers_check_shapes_on_the_host():
+    """The reference helpers reject a power grid or output of another shape
+    before any launch (each wrong buffer here is larger than the right one)."""
+    torch = torch_cuda()
+    say("reference helpers: shape checks")
+    temp = torch.zeros((64, 48), device="cuda")
+    with pytest.raises(ValueError, match="power"):
+        C.reference_hotspot(temp, torch.zeros((65, 48), device="cuda"), 2, STRESS)
+    with pytest.raises(ValueError, match="out"):
+        C.reference_hotspot(temp, torch.zeros((64, 48), device="cuda"), 2, STRESS,
+                            out=torch.zeros((64, 49), device="cuda"))
+    with pytest.raises(ValueError, match="2-D"):
+        C.reference_hotspot(torch.zeros((4, 64, 48), device="cuda"), temp, 2, STRESS)
+    inp = torch.zeros((40, 40), device="cuda")
+    f = torch.zeros((5, 5), device="cuda")
+    with pytest.raises(ValueError, match="out"):
+        C.reference(inp, f, out=torch.zeros((37, 36), device="cuda"))
+    with pytest.raises(ValueError, match="float32"):
+        C.reference(inp, f.double())
+    torch.cuda.synchronize()
