@@ -158,6 +158,10 @@ int conv2d_plan_config(conv2d_plan_t plan, conv2d_config *cfg, int *tuned);
 int conv2d_run(conv2d_plan_t plan, const float *d_in, const float *d_filter, float *d_out,
                void *stream);
 
+/* Frees the plan and unloads its code objects. It does not wait:
+ * the caller first makes sure that no launch of the plan is queued or
+ * running (synchronize the streams it ran on) and that no graph holding its
+ * kernels is replayed afterwards. NULL is ignored. */
 void conv2d_destroy(conv2d_plan_t plan);
 
 /* Plain reference kernel: one thread per output, runtime filter size, the
@@ -212,6 +216,10 @@ int conv2d_batch_run(conv2d_batch_t batch, const float *const *d_in, const float
 int conv2d_batch_info(conv2d_batch_t batch, int *n_groups, int *total_tiles, int *filt,
                       conv2d_config *cfgs, int *grids, int cap);
 
+/* Frees the batch: its code objects and device buffers. It does not wait:
+ * the caller first makes sure that no launch of the batch is queued or
+ * running (synchronize the streams it ran on) and that no graph holding its
+ * kernels is replayed afterwards. NULL is ignored. */
 void conv2d_batch_destroy(conv2d_batch_t batch);
 
 /* Size buckets of the batched path's tuning cache, by the larger output

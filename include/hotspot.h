@@ -110,6 +110,10 @@ int hotspot_plan_config(hotspot_plan_t plan, hotspot_config *cfg, int *tuned);
 int hotspot_run(hotspot_plan_t plan, const float *d_temp, const float *d_power, float *d_out, float *d_work,
                 int steps, hotspot_coeffs k, void *stream);
 
+/* Frees the plan and unloads its code objects. It does not wait:
+ * the caller first makes sure that no launch of the plan is queued or
+ * running (synchronize the streams it ran on) and that no graph holding its
+ * kernels is replayed afterwards. NULL is ignored. */
 void hotspot_destroy(hotspot_plan_t plan);
 
 /* The same computation one step per launch, one cell per thread (the tuner's

@@ -22,6 +22,21 @@ def _check_tensor(t, name, shape=None):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
+def _device():
+    return _torch().cuda.current_device()
+
+
+def _quiesce(device) -> bool:
+    """Waits for the device's queued work, so that a plan's code and memory
+    are freed only once no launch can still use them. False while the
+    current stream captures a graph (the handle is then kept, not freed)."""
+    torch = _torch()
+    if torch.cuda.is_current_stream_capturing():
+        return False
+    torch.cuda.synchronize(device)
+    return True
+
+
 def _stream(stream):
     if stream is None:
         return _torch().cuda.current_stream().cuda_stream
@@ -33,6 +48,7 @@ class Plan:
 
     def __init__(self, out_h, out_w, filt_h, filt_w, config=None):
         self.shape = B.shape(out_h, out_w, filt_h, filt_w)
+        self._device = _device()
         self.handle = B.conv2d_plan(self.shape, config)
         cfg, src = B.conv2d_plan_config(self.handle)
         self.config = cfg.tuple()
@@ -51,7 +67,8 @@ class Plan:
         return out
 
     def close(self):
-        if self.handle:
+        """Frees the plan once its device has finished the queued work."""
+        if self.handle and _quiesce(self._device):
             B.conv2d_destroy(self.handle)
             self.handle = None
 
@@ -97,6 +114,7 @@ class Batch:
 
     def __init__(self, shapes, flags=0):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self._device = _device()
         self.handle = B.conv2d_batch_plan(self.shapes, flags)
         self.info = B.conv2d_batch_info(self.handle)
 
@@ -137,7 +155,8 @@ class Batch:
         return bound
 
     def close(self):
-        if self.handle:
+        """Frees the batch once its device has finished the queued work."""
+        if self.handle and _quiesce(self._device):
             B.conv2d_batch_destroy(self.handle)
             self.handle = None
 
@@ -154,6 +173,7 @@ class Hotspot:
 
     def __init__(self, rows, cols, config=None):
         self.shape = B.hotspot_shape(rows, cols)
+        self._device = _device()
         self.handle = B.hotspot_plan(self.shape, config)
         self.config, tuned = B.hotspot_plan_config(self.handle)
         self.source = "given" if config is not None else {1: "tuned", 2: "tuned-other-grid"}.get(tuned, "default")
@@ -180,7 +200,8 @@ class Hotspot:
         return out
 
     def close(self):
-        if self.handle:
+        """Frees the plan once its device has finished the queued work."""
+        if self.handle and _quiesce(self._device):
             B.hotspot_destroy(self.handle)
             self.handle = None
 

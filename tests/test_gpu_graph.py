@@ -101,3 +101,50 @@ def test_plan_shared_by_threads_on_their_own_streams():
     assert not any(t.is_alive() for t in threads)
     assert not errors, errors
     plan.close()
+
+
+def test_close_waits_for_queued_work_and_keeps_a_captured_plan():
+    """A plan dropped right after an asynchronous call (a temporary object)
+    frees its code only after the device has finished the queued work: the
+    output still equals a kept plan's, bit for bit. close() inside a capture
+    keeps the handle, the graph replays, and a later close() frees it."""
+    import gc
+    torch = torch_cuda()
+    H, W, fh, fw = 700, 640, 17, 17
+    inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=61, seed_f=62)
+    di, df = to_dev(inp), to_dev(f)
+    keep = C.Plan(H, W, fh, fw)
+    want = keep(di, df)
+    torch.cuda.synchronize()
+    want = want.cpu().numpy().copy()
+    say("temporary plans closed with queued work")
+    outs = []
+    for _ in range(4):
+        junk = torch.randn(1 << 22, device="cuda")              # queued work ahead of the launch
+        outs.append(C.Plan(H, W, fh, fw, config=(64, 2, 4, 4, 1, 0, 1))(di, df))
+        gc.collect()
+        del junk
+    torch.cuda.synchronize()
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy().view(np.uint32), want.view(np.uint32))
+
+    say("close inside a capture")
+    plan = C.Plan(H, W, fh, fw, config=(16, 16, 1, 1, 1, 1, 1))
+    out = torch.full((H, W), float("nan"), device="cuda")
+    plan(di, df, out=out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan(di, df, out=out)
+        plan.close()
+        assert plan.handle                                     # kept while capturing
+    for rep in range(3):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), want.view(np.uint32)), rep
+    del g
+    plan.close()
+    assert not plan.handle
+    keep.close()
