@@ -296,7 +296,9 @@ int conv2d_compile_batch(conv2d_shape s, const conv2d_config *cfg, char *path_ou
  * bitwise identical to a plain conv2d_run of the same data. */
 
 typedef struct conv2d_request {
-    double arrival_s;       /* seconds from the start of the run, non-decreasing */
+    double arrival_s;       /* seconds from the start of the run: finite, >= 0 and
+                               non-decreasing (else CONV2D_EINVAL, before any
+                               device work) */
     conv2d_shape shape;
     uint64_t seed_in;       /* image seed */
     uint64_t seed_f;        /* filter seed */

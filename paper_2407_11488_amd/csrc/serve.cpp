@@ -156,8 +156,6 @@ public:
             r.bytes = align_up(r.n_in * 4) + align_up(r.n_f * 4) + (o_.keep_outputs ? 0 : align_up(r.n_out * 4));
             if (r.bytes > o_.hbm_budget)
                 return fail(CONV2D_EINVAL, "request " + std::to_string(i) + " alone exceeds the HBM budget");
-            if (i > 0 && rq_[i].arrival_s < rq_[i - 1].arrival_s)
-                return fail(CONV2D_EINVAL, "arrival times must be non-decreasing");
             // Kernels for every filter size and size bucket of the trace are
             // built up front (buckets that share a configuration share one).
             if (!o_.serial_plain) {
@@ -521,6 +519,13 @@ extern "C" int conv2d_serve(const conv2d_request* reqs, int n, const conv2d_serv
     if (o.max_batch < 1 || o.max_batch > 32767) return fail(CONV2D_EINVAL, "serve: max_batch must be in 1..32767");
     if (o.hbm_budget < (1ull << 20)) return fail(CONV2D_EINVAL, "serve: HBM budget below 1 MiB");
     if (o.keep_outputs && !outputs) return fail(CONV2D_EINVAL, "serve: keep_outputs needs an outputs array");
+    for (int i = 0; i < n; ++i) {
+        const double t = reqs[i].arrival_s;
+        if (!std::isfinite(t) || t < 0.0)
+            return fail(CONV2D_EINVAL, "serve: request " + std::to_string(i) + " has no finite arrival time >= 0");
+        if (i > 0 && t < reqs[i - 1].arrival_s)
+            return fail(CONV2D_EINVAL, "serve: arrival times must be non-decreasing");
+    }
     auto s = std::make_unique<Server>(reqs, n, o);
     int rc = s->init();
     if (!rc) rc = s->run(rep, latency_ms, outputs);

@@ -372,3 +372,12 @@ def test_bench_traffic_record_matches_only_its_kernel():
     win = C.conv2d_cache_lookup(os.path.join(ROOT, "paper_2407_11488_amd", "tuned", "winners.jsonl"), "gfx950",
                                 C.shape(4096, 4096, 17, 17))
     assert win is not None and win[0].tuple() == tuple(rec["config"])
+
+
+@pytest.mark.parametrize("arrivals", [(0.0, float("nan")), (-1.0, 0.0), (0.0, float("inf")), (0.5, 0.25)])
+def test_serve_rejects_bad_arrival_times_before_device_work(arrivals):
+    """Arrival times must be finite, >= 0 and non-decreasing; the check runs
+    before the device is queried, so it holds without a GPU."""
+    reqs = C.requests_array(list(arrivals), [(64, 64, 3, 3)] * len(arrivals), [1, 2], [3, 4])
+    with pytest.raises(RuntimeError, match="arrival"):
+        C.conv2d_serve(reqs)
