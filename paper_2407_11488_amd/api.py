@@ -147,10 +147,12 @@ class Batch:
         n = len(self.shapes)
         keep = (list(inputs), list(filters), list(outputs))
         arrays = [(ctypes.c_void_p * n)(*[t.data_ptr() for t in ts]) for ts in keep]
-        handle, run = self.handle, B.lib.conv2d_batch_run
+        run = B.lib.conv2d_batch_run
 
         def bound(stream=None):
-            B.check(run(handle, *arrays, _stream(stream)), "conv2d_batch_run")
+            # the handle is read at each call: after close() it is None, which
+            # the library rejects
+            B.check(run(self.handle, *arrays, _stream(stream)), "conv2d_batch_run")
             return keep[2]
         return bound
 

@@ -108,6 +108,9 @@ def test_graph_replays_and_pointer_changes(workload):
         for a, o in zip(first, outs3):
             assert np.array_equal(a.view(np.uint32), o.cpu().numpy().view(np.uint32))
     again.close()
+    assert not again.handle
+    with pytest.raises(RuntimeError, match="non-NULL"):   # a bound run after close() is refused
+        run()
 
 
 def test_batch_edge_cases():
