@@ -12,10 +12,12 @@ def _torch():
     return torch
 
 
-def _check_tensor(t, name, shape=None):
+def _check_tensor(t, name, shape=None, device=None):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, expected cuda:{device}")
     if t.dtype != torch.float32 or not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous float32")
     if shape is not None and tuple(t.shape) != tuple(shape):
@@ -58,11 +60,11 @@ class Plan:
     def __call__(self, inp, filt, out=None, stream=None):
         torch = _torch()
         H, W, fh, fw = self.shape.tuple()
-        _check_tensor(inp, "inp", (H + fh - 1, W + fw - 1))
-        _check_tensor(filt, "filt", (fh, fw))
+        _check_tensor(inp, "inp", (H + fh - 1, W + fw - 1), self._device)
+        _check_tensor(filt, "filt", (fh, fw), self._device)
         if out is None:
             out = torch.empty((H, W), dtype=torch.float32, device=inp.device)
-        _check_tensor(out, "out", (H, W))
+        _check_tensor(out, "out", (H, W), self._device)
         B.conv2d_run(self.handle, inp.data_ptr(), filt.data_ptr(), out.data_ptr(), _stream(stream))
         return out
 
@@ -86,7 +88,7 @@ def conv2d(inp, filt, config=None, out=None, stream=None):
     """One convolution; plans are cached per (shape, config)."""
     fh, fw = filt.shape
     H, W = inp.shape[0] - fh + 1, inp.shape[1] - fw + 1
-    key = (H, W, fh, fw, None if config is None else tuple(B.config(config).tuple()))
+    key = (_device(), H, W, fh, fw, None if config is None else tuple(B.config(config).tuple()))
     plan = _plans.get(key)
     if plan is None:
         plan = _plans[key] = Plan(H, W, fh, fw, config)
@@ -96,15 +98,16 @@ def conv2d(inp, filt, config=None, out=None, stream=None):
 def reference(inp, filt, out=None, stream=None):
     """The library's plain reference kernel (one thread per output)."""
     torch = _torch()
-    _check_tensor(inp, "inp")
-    _check_tensor(filt, "filt")
+    dev = _device()
+    _check_tensor(inp, "inp", device=dev)
+    _check_tensor(filt, "filt", device=dev)
     if inp.dim() != 2 or filt.dim() != 2:
         raise ValueError("inp and filt must be 2-D")
     fh, fw = filt.shape
     H, W = inp.shape[0] - fh + 1, inp.shape[1] - fw + 1
     if out is None:
         out = torch.empty((H, W), dtype=torch.float32, device=inp.device)
-    _check_tensor(out, "out", (H, W))
+    _check_tensor(out, "out", (H, W), dev)
     B.conv2d_reference(B.shape(H, W, fh, fw), inp.data_ptr(), filt.data_ptr(), out.data_ptr(), _stream(stream))
     return out
 
@@ -126,9 +129,9 @@ class Batch:
             outputs = [torch.empty((H, W), dtype=torch.float32, device=inputs[0].device)
                        for (H, W, _, _) in self.shapes]
         for k, (H, W, fh, fw) in enumerate(self.shapes):
-            _check_tensor(inputs[k], f"inputs[{k}]", (H + fh - 1, W + fw - 1))
-            _check_tensor(filters[k], f"filters[{k}]", (fh, fw))
-            _check_tensor(outputs[k], f"outputs[{k}]", (H, W))
+            _check_tensor(inputs[k], f"inputs[{k}]", (H + fh - 1, W + fw - 1), self._device)
+            _check_tensor(filters[k], f"filters[{k}]", (fh, fw), self._device)
+            _check_tensor(outputs[k], f"outputs[{k}]", (H, W), self._device)
         B.conv2d_batch_run(self.handle, [t.data_ptr() for t in inputs], [t.data_ptr() for t in filters],
                            [t.data_ptr() for t in outputs], _stream(stream))
         return outputs
@@ -141,9 +144,9 @@ class Batch:
         if len(inputs) != len(self.shapes) or len(filters) != len(self.shapes) or len(outputs) != len(self.shapes):
             raise ValueError("one input, filter and output per problem")
         for k, (H, W, fh, fw) in enumerate(self.shapes):
-            _check_tensor(inputs[k], f"inputs[{k}]", (H + fh - 1, W + fw - 1))
-            _check_tensor(filters[k], f"filters[{k}]", (fh, fw))
-            _check_tensor(outputs[k], f"outputs[{k}]", (H, W))
+            _check_tensor(inputs[k], f"inputs[{k}]", (H + fh - 1, W + fw - 1), self._device)
+            _check_tensor(filters[k], f"filters[{k}]", (fh, fw), self._device)
+            _check_tensor(outputs[k], f"outputs[{k}]", (H, W), self._device)
         n = len(self.shapes)
         keep = (list(inputs), list(filters), list(outputs))
         arrays = [(ctypes.c_void_p * n)(*[t.data_ptr() for t in ts]) for ts in keep]
@@ -187,11 +190,11 @@ class Hotspot:
         streams must not overlap."""
         torch = _torch()
         shp = (self.shape.rows, self.shape.cols)
-        _check_tensor(temp, "temp", shp)
-        _check_tensor(power, "power", shp)
+        _check_tensor(temp, "temp", shp, self._device)
+        _check_tensor(power, "power", shp, self._device)
         if out is None:
             out = torch.empty(shp, dtype=torch.float32, device=temp.device)
-        _check_tensor(out, "out", shp)
+        _check_tensor(out, "out", shp, self._device)
         work = 0
         if steps > self.config[4]:
             if self._work is None or self._work.device != temp.device:
@@ -217,14 +220,15 @@ class Hotspot:
 def reference_hotspot(temp, power, steps, coeffs, out=None, stream=None):
     """The library's one-step-per-launch hotspot reference."""
     torch = _torch()
-    _check_tensor(temp, "temp")
+    dev = _device()
+    _check_tensor(temp, "temp", device=dev)
     if temp.dim() != 2:
         raise ValueError("temp must be 2-D")
     rows, cols = temp.shape
-    _check_tensor(power, "power", (rows, cols))
+    _check_tensor(power, "power", (rows, cols), dev)
     if out is None:
         out = torch.empty((rows, cols), dtype=torch.float32, device=temp.device)
-    _check_tensor(out, "out", (rows, cols))
+    _check_tensor(out, "out", (rows, cols), dev)
     # torch's caching allocator keeps the work buffer's memory for this
     # stream until the stream has passed the launches
     work = torch.empty((rows, cols), dtype=torch.float32, device=temp.device) if steps > 1 else None
