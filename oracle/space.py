@@ -36,11 +36,13 @@ def restricted():
 
 # The hotspot space: the MI355X version of Table 1's hotspot parameters
 # (block sizes for wave64, per-thread tiles, temporal tiling factor, step-loop
-# unroll, power staging), restricted to 64..1024 threads, a region of
+# unroll, power staging), restricted to 64..1024 threads and a region of
 # (block_y*tile_y) x (block_x*tile_x) cells larger than twice the temporal
-# factor along both axes (a non-empty output tile), and two LDS buffers of
-# (rows + 2) x ((cols + 2) | 1) floats (the region and a one-cell ring, odd
-# pitch) within 160 KiB (never binding here: at most 147,888 bytes).
+# factor along both axes (a non-empty output tile once the halo of
+# `temporal` cells per side is taken off). Table 1 prints no memory
+# restriction; the library also checks a configuration's LDS size against the
+# device limit, which no point of these axes reaches, so it is not part of
+# this definition.
 HOTSPOT_AXES = (
     ("block_x", (16, 32, 64, 128, 256)),
     ("block_y", (1, 2, 4, 8, 16)),
@@ -50,7 +52,6 @@ HOTSPOT_AXES = (
     ("unroll_t", (0, 1)),
     ("sh_power", (0, 1)),
 )
-HOTSPOT_LDS_LIMIT = 163840
 
 
 def hotspot_restricted():
@@ -61,8 +62,6 @@ def hotspot_restricted():
         if not 64 <= bx * by <= MAX_THREADS:
             continue
         if rows <= 2 * tt or cols <= 2 * tt:
-            continue
-        if 2 * (rows + 2) * ((cols + 2) | 1) * 4 > HOTSPOT_LDS_LIMIT:
             continue
         out.append(c)
     return out

@@ -133,3 +133,145 @@ def test_results_analysis_matches_the_statistics_oracle(tmp_path):
         return tuning.performance_portability(effs)
     want = max(sorted(common), key=pp)
     assert cfg == want and row["pp"] == pytest.approx(pp(want), rel=1e-12)
+
+
+# ------------------------------------------------ local search, worked by hand
+#
+# A 4 x 3 lattice (axes a in 0..3, b in 0..2; enumeration order (0,0), (0,1),
+# ..., (3,2)); point (3,1) fails. Times:
+#
+#          b=0   b=1   b=2
+#   a=0    5     4     6
+#   a=1    7     3     8
+#   a=2    9     2     7
+#   a=3    1.5   fail  10
+#
+# Seed 1. Restart k starts at the idx-th unevaluated point in enumeration
+# order, idx = splitmix64(1, k) mod count (the counter-form values are
+# 0x910a2dec89025cc1, 0xbeeb8da1658eec67, 0xf893a2eefb32555e,
+# 0x71c18690ee42c90b: mod 12 = 5, mod 3 = 1, mod 2 = 0, mod 1 = 0).
+#
+# restart 0: 12 fresh, idx 5 -> (1,2) = 8. Its neighbours, axis by axis,
+#   lower value first: (0,2) = 6, (2,2) = 7, (1,1) = 3 (no (1,3)); the best,
+#   (1,1), improves -> move.  (1,1): new neighbours (0,1) = 4, (2,1) = 2,
+#   (1,0) = 7 ((1,2) already known); best (2,1) = 2 < 3 -> move.  (2,1): new
+#   (3,1) fails, (2,0) = 9; known (1,1) = 3, (2,2) = 7; best 3 is not below 2
+#   -> local minimum. 9 evaluations.
+# restart 1: fresh (0,0), (3,0), (3,2); idx 1 -> (3,0) = 1.5. Neighbours
+#   (2,0) = 9 and (3,1) failed: no move. 10 evaluations.
+# restart 2: fresh (0,0), (3,2); idx 0 -> (0,0) = 5, then (0,1) = 4 -> (1,1)
+#   -> (2,1), all known: no new evaluation. 11 evaluations.
+# restart 3: fresh (3,2); idx 0 -> (3,2) = 10 -> (2,2) -> (2,1). 12, and no
+#   fresh point is left.
+#
+# A first-improvement walk would leave (1,2) for (0,2), the first improving
+# neighbour, and evaluate (0,0) sixth instead of (2,1).
+
+HAND_AXES = [[0, 1, 2, 3], [0, 1, 2]]
+HAND_LEGAL = [(a, b) for a in range(4) for b in range(3)]
+HAND_TIMES = {(0, 0): 5.0, (0, 1): 4.0, (0, 2): 6.0, (1, 0): 7.0, (1, 1): 3.0, (1, 2): 8.0,
+              (2, 0): 9.0, (2, 1): 2.0, (2, 2): 7.0, (3, 0): 1.5, (3, 1): None, (3, 2): 10.0}
+HAND_ORDER = [(1, 2), (0, 2), (2, 2), (1, 1), (0, 1), (2, 1), (1, 0), (3, 1), (2, 0), (3, 0), (0, 0), (3, 2)]
+
+
+def _hand_case_holds(local_search):
+    """True when a local-search implementation reproduces every figure of the
+    walk worked by hand above."""
+    for budget, best in ((100, (3, 0)), (12, (3, 0)), (10, (3, 0)), (9, (2, 1)), (4, (1, 1)), (1, (1, 2))):
+        got_best, order = local_search(HAND_TIMES, HAND_LEGAL, HAND_AXES, budget, 1)
+        if order != HAND_ORDER[:budget] or got_best != best:
+            return False
+    return True
+
+
+def test_splitmix_restart_indices_of_the_hand_case():
+    import numpy as np
+
+    from datagen import splitmix64
+    z = [int(v) for v in splitmix64(1, np.arange(4, dtype=np.uint64))]
+    assert z == [0x910a2dec89025cc1, 0xbeeb8da1658eec67, 0xf893a2eefb32555e, 0x71c18690ee42c90b]
+    assert (z[0] % 12, z[1] % 3, z[2] % 2, z[3] % 1) == (5, 1, 0, 0)
+
+
+def test_local_search_walk_worked_by_hand():
+    assert _hand_case_holds(tuning.local_search)
+
+
+def _mutant(old: str, new: str):
+    """tuning.local_search with one line of its source replaced."""
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(tuning.local_search))
+    assert src.count(old) == 1, old
+    ns = {"np": __import__("numpy")}
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    return ns["local_search"]
+
+
+@pytest.mark.parametrize("old,new", [
+    # first improvement: move to the first improving neighbour in order
+    ("nxt = min(ok, key=lambda c: (state[c], c))",
+     "nxt = next((n for n in ok if state[n] < state[cur]), cur)"),
+    # restart index off by one
+    ("np.array([restart], dtype=np.uint64)", "np.array([restart + 1], dtype=np.uint64)"),
+    # start counted over every legal point instead of the unevaluated ones
+    ("cur = fresh[z % len(fresh)]", "cur = legal[z % len(legal)]"),
+    # neighbours higher value first
+    ("for q in (pos - 1, pos + 1):", "for q in (pos + 1, pos - 1):"),
+    # every restart from the stream's first value
+    ("np.array([restart], dtype=np.uint64)", "np.array([0], dtype=np.uint64)"),
+    # the last point evaluated reported instead of the best
+    ("return min(ok, key=lambda c: (state[c], c)), order", "return order[-1], order"),
+])
+def test_local_search_mutants_fail_the_hand_case(old, new):
+    assert not _hand_case_holds(_mutant(old, new))
+
+
+# ------------------------------------------------ hotspot space, counted by hand
+#
+# Axes: block_x in {16, 32, 64, 128, 256}, block_y in {1, 2, 4, 8, 16},
+# tile_x, tile_y in {1, 2, 4}, temporal in {1, 2, 3, 4, 6, 8}, and two on/off
+# switches (step-loop unroll, power on chip) that no restriction reads (x4).
+# Restrictions: 64 <= block_x*block_y <= 1024; the region of
+# (block_y*tile_y) x (block_x*tile_x) cells larger than 2*temporal on both axes.
+#
+# Blocks with 64..1024 threads: 16 x {4, 8, 16}, 32 x {2, 4, 8, 16},
+# 64 x {1, ..., 16}, 128 x {1, 2, 4, 8}, 256 x {1, 2, 4}: 19 pairs.
+# Legal tile_y per (block_y, temporal), temporal 1, 2, 3, 4, 6, 8 (2t = 2, 4,
+# 6, 8, 12, 16; rows = block_y*tile_y must exceed 2t):
+#   block_y 1: rows 1, 2, 4           -> 1 0 0 0 0 0
+#   block_y 2: rows 2, 4, 8           -> 2 1 1 0 0 0
+#   block_y 4: rows 4, 8, 16          -> 3 2 2 1 1 0
+#   block_y 8: rows 8, 16, 32         -> 3 3 3 2 2 1
+#   block_y 16: rows 16, 32, 64       -> 3 3 3 3 3 2
+# Legal tile_x per (block_x, temporal): block_x 16 gives columns 16, 32, 64
+# -> 3 3 3 3 3 2; block_x >= 32 gives at least 32 columns -> 3 everywhere.
+# Sum over blocks of tile_x count * tile_y count:
+#   16 x 4: 27, 16 x 8: 41, 16 x 16: 49                      -> 117
+#   32 x {2, 4, 8, 16}: 3 * (4 + 9 + 14 + 17)                -> 132
+#   64 x {1, ..., 16}: 3 * (1 + 4 + 9 + 14 + 17)             -> 135
+#   128 x {1, 2, 4, 8}: 3 * (1 + 4 + 9 + 14)                 -> 84
+#   256 x {1, 2, 4}: 3 * (1 + 4 + 9)                         -> 42
+# 510 (block, tile, temporal) points, x4 switches = 2,040.
+
+HAND_TY = {1: [1, 0, 0, 0, 0, 0], 2: [2, 1, 1, 0, 0, 0], 4: [3, 2, 2, 1, 1, 0],
+           8: [3, 3, 3, 2, 2, 1], 16: [3, 3, 3, 3, 3, 2]}
+HAND_TX = {16: [3, 3, 3, 3, 3, 2], 32: [3] * 6, 64: [3] * 6, 128: [3] * 6, 256: [3] * 6}
+HAND_BLOCKS = {16: (4, 8, 16), 32: (2, 4, 8, 16), 64: (1, 2, 4, 8, 16), 128: (1, 2, 4, 8), 256: (1, 2, 4)}
+TEMPORAL = (1, 2, 3, 4, 6, 8)
+
+
+def test_hotspot_space_count_by_hand():
+    from collections import Counter
+    got = Counter((c[0], c[1], c[4]) for c in space.hotspot_restricted())
+    want = {}
+    for bx, bys in HAND_BLOCKS.items():
+        for by in bys:
+            for k, t in enumerate(TEMPORAL):
+                n = 4 * HAND_TX[bx][k] * HAND_TY[by][k]
+                if n:
+                    want[(bx, by, t)] = n
+    assert dict(got) == want
+    assert sum(want.values()) == 2040 == len(space.hotspot_restricted())
+    assert [sum(4 * HAND_TX[bx][k] * HAND_TY[by][k] for by in bys for k in range(6))
+            for bx, bys in HAND_BLOCKS.items()] == [4 * 117, 4 * 132, 4 * 135, 4 * 84, 4 * 42]
