@@ -77,53 +77,80 @@ typedef struct conv2d_batch_s *conv2d_batch_t;
 /* ---------------------------------------------------------------- host only
  * These never touch a GPU and can be called on a machine without one. */
 
-/* Library version (major*10000 + minor*100 + patch). */
+/* Library version (major*10000 + minor*100 + patch).
+ * Source: none in the paper (library metadata). */
 int conv2d_version(void);
 
-/* Thread-local text of the last non-zero return on this thread ("" if none). */
+/* Thread-local text of the last non-zero return on this thread ("" if none).
+ * Source: none in the paper (this ABI's error reporting). */
 const char *conv2d_last_error(void);
 
 /* Hex hash of the tunable kernel source built into this library, taken over
  * its code with comments and blank runs removed (keys the winners cache and
  * the tuner's results; editing comments keeps them valid). Static storage,
- * never NULL. */
+ * never NULL.
+ * Source: none in the paper (the key under which this library stores what
+ * the Section 3 measurements found). */
 const char *conv2d_kernel_hash(void);
 
 /* The untuned default configuration: the textbook 16x16-thread tiled kernel,
- * one output per thread, LDS halo, filter in constant memory, unroll 1. */
+ * one output per thread, LDS halo, filter in constant memory, unroll 1.
+ * Source: Section 4 measures tuning against the space's median; this fixed
+ * point of the Table 1 space is the library's second baseline (tuned/default). */
 void conv2d_default_config(conv2d_config *cfg);
 
-/* LDS bytes a configuration needs for a filter size (0 when use_lds = 0). */
+/* LDS bytes a configuration needs for a filter size (0 when use_lds = 0).
+ * Source: Table 1 (use_shmem: the input halo staged in shared memory). */
 int conv2d_lds_bytes(int filt_h, int filt_w, const conv2d_config *cfg);
 
 /* Legality of a configuration for a shape: axis values in range,
  * block_x*block_y <= 1024, LDS bytes <= lds_limit (pass 0 for the gfx950
- * value, 163840). Returns CONV2D_OK or CONV2D_EINVAL with a reason. */
+ * value, 163840). Returns CONV2D_OK or CONV2D_EINVAL with a reason.
+ * Source: Table 1 (the parameter values); the paper does not print its
+ * restrictions, only the restricted space's size (Table 3). */
 int conv2d_config_check(conv2d_shape s, const conv2d_config *cfg, int lds_limit);
 
 /* Enumerates the restricted search space for a shape in axis order
  * (block_x, block_y, tile_x, tile_y, use_lds, filter_in_const), with the given
  * unroll for every point; writes up to `cap` configurations to `out` (may be
  * NULL) and returns the number of legal points (or a negative status).
- * With lds_limit < 0 only the thread-count restriction is applied. */
+ * With lds_limit < 0 only the thread-count restriction is applied.
+ * Source: Table 1 (the convolution's tunable parameters) and Table 3 (the
+ * search-space size row). */
 int conv2d_space(conv2d_shape s, int unroll, int lds_limit, conv2d_config *out, int cap);
 
 /* Compiles one configuration for gfx950 with hiprtc into the code-object
  * cache (no GPU needed). vec_in/vec_out are the alignment classes 1, 2 or 4.
  * Writes the cache file path to path_out (if non-NULL, cap bytes).
- * Returns CONV2D_OK or CONV2D_ECOMPILE (log in last_error). */
+ * Returns CONV2D_OK or CONV2D_ECOMPILE (log in last_error).
+ * Source: Section 3 (each configuration is compiled before it is benchmarked). */
 int conv2d_compile(conv2d_shape s, const conv2d_config *cfg, int vec_in, int vec_out,
                    char *path_out, int path_cap);
 
+/* Fills the code-object cache from a manifest: a text file with one program
+ * per line (its file name, conv2d_direct.hip or hotspot.hip, then its hiprtc
+ * options, separated by spaces; '#' starts a comment line), as a process
+ * writes it to the file named by the environment variable CONV2D_COMPILE_LOG.
+ * Compiles each program not yet cached on up to `threads` host threads (0:
+ * all), no GPU needed, so that a later run on a GPU compiles nothing.
+ * *n_compiled and *n_cached (may be NULL) receive the counts. Returns
+ * CONV2D_OK, CONV2D_EINVAL (unreadable file, unknown program) or
+ * CONV2D_ECOMPILE (entries that failed; the first log in last_error).
+ * Source: none in the paper (a build step of this library). */
+int conv2d_warm_cache(const char *manifest, int threads, int *n_compiled, int *n_cached);
+
 /* Launch geometry of a configuration: tiles along x and y for one band of
  * rows (the kernel covers the output with tiles of
- * (block_x*tile_x) x (block_y*tile_y), one workgroup per tile). */
+ * (block_x*tile_x) x (block_y*tile_y), one workgroup per tile).
+ * Source: Table 1 (block_size_x/y threads, tile_size_x/y outputs per thread). */
 int conv2d_geometry(conv2d_shape s, const conv2d_config *cfg, int *tiles_x, int *tiles_y,
                     int *threads_per_block);
 
 /* Winners cache (JSON lines; the last line for a key wins). Key: GPU arch,
  * shape, and the kernel source hash. arch may be NULL for the current
- * device's arch. lookup returns CONV2D_ENOTUNED when absent. */
+ * device's arch. lookup returns CONV2D_ENOTUNED when absent.
+ * Source: Section 6 (one tuned configuration per kernel and device, Tables
+ * 4-5); the file format is this library's. */
 int conv2d_cache_lookup(const char *path, const char *arch, conv2d_shape s,
                         conv2d_config *cfg, double *ms);
 int conv2d_cache_store(const char *path, const char *arch, conv2d_shape s,
@@ -138,13 +165,16 @@ int conv2d_cache_store(const char *path, const char *arch, conv2d_shape s,
  * recent) when it is legal for this shape, else the default
  * configuration; the environment variable CONV2D_FORCE_CONFIG
  * ("bx,by,tx,ty,lds,const,unroll") overrides both. Compiles (or loads from the
- * code-object cache) and loads the module. The plan owns the module. */
+ * code-object cache) and loads the module. The plan owns the module.
+ * Source: Section 5 (the convolution benchmark kernel) with a point of the
+ * Table 1 space; the formula is the one at the top of this header. */
 int conv2d_plan(conv2d_plan_t *plan, conv2d_shape s, const conv2d_config *cfg);
 
 /* The configuration a plan uses, and whether it came from the winners cache
  * (*tuned = 1; 3 when that entry was tuned with an older revision of the
  * kernel source; 4 when it is the same filter's winner for another shape),
- * was forced or given (2), or is the default (0). */
+ * was forced or given (2), or is the default (0).
+ * Source: Table 1 (the parameters of the configuration). */
 int conv2d_plan_config(conv2d_plan_t plan, conv2d_config *cfg, int *tuned);
 
 /* Enqueues one convolution on `stream`. With filter_in_const = 1 the filter is
@@ -154,25 +184,32 @@ int conv2d_plan_config(conv2d_plan_t plan, conv2d_config *cfg, int *tuned);
  * filter goes to constant memory, then the kernel node); replays read the
  * buffers' current contents. Capture a call whose pointers are aligned as the
  * plan's first run will be, or run it once first: the first misaligned call
- * compiles a second module. */
+ * compiles a second module.
+ * Source: Section 5 (the convolution benchmark kernel); Table 1 (read_only,
+ * use_shmem, tile and block sizes select the variant enqueued). */
 int conv2d_run(conv2d_plan_t plan, const float *d_in, const float *d_filter, float *d_out,
                void *stream);
 
 /* Frees the plan and unloads its code objects. It does not wait:
  * the caller first makes sure that no launch of the plan is queued or
  * running (synchronize the streams it ran on) and that no graph holding its
- * kernels is replayed afterwards. NULL is ignored. */
+ * kernels is replayed afterwards. NULL is ignored.
+ * Source: none in the paper (resource release of this ABI). */
 void conv2d_destroy(conv2d_plan_t plan);
 
 /* Plain reference kernel: one thread per output, runtime filter size, the
  * same accumulation order as every configuration. Used by the tuner to verify
- * each configuration bitwise. */
+ * each configuration bitwise.
+ * Source: Section 5 (the convolution kernel's result, computed without
+ * tiling); the tuner checks results before timing them (Section 3). */
 int conv2d_reference(conv2d_shape s, const float *d_in, const float *d_filter, float *d_out,
                      void *stream);
 
 /* Fills n floats of device memory with the seeded uniform values of the
  * splitmix64 recipe (hash element start+k of `seed`, mapped to
- * (top24 - 2^23) * 2^-23), on `stream`. */
+ * (top24 - 2^23) * 2^-23), on `stream`.
+ * Source: none in the paper (synthetic inputs; the paper's inputs are in its
+ * unavailable companion repository, Section 5). */
 int conv2d_fill_uniform(float *d_out, size_t n, uint64_t seed, uint64_t start, void *stream);
 
 /* ---------------------------------------------------------------- batched path
@@ -199,27 +236,33 @@ enum {
     CONV2D_BATCH_BY_SIZE = 4       /* each problem takes its size bucket's configuration */
 };
 
-/* Plans n problems (n <= 65535); shapes[i] as for conv2d_plan. */
+/* Plans n problems (n <= 65535); shapes[i] as for conv2d_plan.
+ * Source: Section 5 (the convolution kernel, applied to many problems);
+ * batching is this library's extension, not the paper's. */
 int conv2d_batch_plan(conv2d_batch_t *batch, int n, const conv2d_shape *shapes, int flags);
 
 /* Enqueues all n convolutions on `stream`: d_in[i], d_f[i], d_out[i] are the
  * device buffers of problem i (host arrays of n device pointers). When the
  * pointers differ from the previous run, a 48-byte-per-problem descriptor
- * table is first copied to the device on the same stream. */
+ * table is first copied to the device on the same stream.
+ * Source: Section 5 (the convolution kernel); batching is this library's
+ * extension. */
 int conv2d_batch_run(conv2d_batch_t batch, const float *const *d_in, const float *const *d_f,
                      float *const *d_out, void *stream);
 
 /* Groups of a batch: their count, the total tile count, and for the first
  * `cap` groups the filter size (filt[2g], filt[2g+1]), configuration and
  * grid size (one workgroup per tile, at least 8). Any output pointer may be
- * NULL. */
+ * NULL.
+ * Source: Table 1 (the configuration of each group). */
 int conv2d_batch_info(conv2d_batch_t batch, int *n_groups, int *total_tiles, int *filt,
                       conv2d_config *cfgs, int *grids, int cap);
 
 /* Frees the batch: its code objects and device buffers. It does not wait:
  * the caller first makes sure that no launch of the batch is queued or
  * running (synchronize the streams it ran on) and that no graph holding its
- * kernels is replayed afterwards. NULL is ignored. */
+ * kernels is replayed afterwards. NULL is ignored.
+ * Source: none in the paper (resource release of this ABI). */
 void conv2d_batch_destroy(conv2d_batch_t batch);
 
 /* Size buckets of the batched path's tuning cache, by the larger output
@@ -227,7 +270,8 @@ void conv2d_batch_destroy(conv2d_batch_t batch);
 #define CONV2D_SIZE_BUCKETS 5
 
 /* The size bucket (1..CONV2D_SIZE_BUCKETS) of an out_h x out_w output
- * (host only; sides of 0 or less give bucket 1). */
+ * (host only; sides of 0 or less give bucket 1).
+ * Source: none in the paper (the served workload's size classes). */
 int conv2d_size_bucket(int out_h, int out_w);
 
 /* Tunes the batched path on a batch: the problems are grouped by filter size
@@ -244,7 +288,9 @@ int conv2d_size_bucket(int out_h, int out_w);
  * conv2d_serve and CONV2D_BATCH_BY_SIZE plans the second). Candidates are
  * compiled on up
  * to 16 host threads first. Not part of the paper (its tuner tunes one kernel
- * on one problem); this is the batched path's own tuning. */
+ * on one problem); this is the batched path's own tuning.
+ * Source: Section 3 (event timing of each compiled configuration) applied to
+ * the batched kernel; Table 1 (the candidates' parameters). */
 #define CONV2D_BATCH_TUNE_MAX 32
 typedef struct conv2d_batch_tune_opts {
     const char *winners_path;  /* winners cache read and appended (NULL: $CONV2D_WINNERS or the default) */
@@ -263,18 +309,22 @@ typedef struct conv2d_batch_tune_result {
     int n_problems[CONV2D_BATCH_TUNE_MAX];         /* problems of the batch in group g */
     conv2d_config before[CONV2D_BATCH_TUNE_MAX];   /* the choice before tuning */
     conv2d_config after[CONV2D_BATCH_TUNE_MAX];    /* the winner */
-    double before_ms[CONV2D_BATCH_TUNE_MAX];       /* the group's kernel, sustained, ms per launch */
+    double before_ms[CONV2D_BATCH_TUNE_MAX];       /* the group's kernel, sustained, ms per launch
+                                                      (-1: the choice before tuning did not build or
+                                                      verify, so it has no time) */
     double after_ms[CONV2D_BATCH_TUNE_MAX];
     int n_tried[CONV2D_BATCH_TUNE_MAX];            /* candidates that compiled, ran and verified */
 } conv2d_batch_tune_result;
 
+/* Source: none in the paper (option defaults). */
 void conv2d_batch_tune_defaults(conv2d_batch_tune_opts *opts);
 int conv2d_batch_tune(int n, const conv2d_shape *shapes, const conv2d_batch_tune_opts *opts,
                       conv2d_batch_tune_result *res);
 
 /* Compiles the batched kernel of a configuration (filter read through its
  * pointer, scalar loads and stores) for gfx950 with hiprtc, no GPU needed.
- * Only s.filt_h and s.filt_w matter. */
+ * Only s.filt_h and s.filt_w matter.
+ * Source: Section 3 (compilation of each configuration). */
 int conv2d_compile_batch(conv2d_shape s, const conv2d_config *cfg, char *path_out, int path_cap);
 
 /* ---------------------------------------------------------------- serving
@@ -324,14 +374,20 @@ typedef struct conv2d_serve_report {
     double late_start_ms;   /* serial run: worst launch delay behind schedule */
 } conv2d_serve_report;
 
+/* Source: none in the paper (option defaults). */
 void conv2d_serve_defaults(conv2d_serve_opts *opts);
 
 /* Runs reqs[0..n) (blocking). latency_ms (may be NULL) receives each
  * request's latency; with keep_outputs, outputs[i] receives a device pointer
- * to request i's output (release with conv2d_serve_free). */
+ * to request i's output (release with conv2d_serve_free).
+ * Source: Section 5 (the convolution kernel) served to a request stream;
+ * serving is this library's extension, not the paper's. */
 int conv2d_serve(const conv2d_request *reqs, int n, const conv2d_serve_opts *opts,
                  conv2d_serve_report *report, double *latency_ms, float **outputs);
 
+/* Frees outputs[0..n) returned by conv2d_serve with keep_outputs (NULL
+ * entries are skipped). It does not wait for the device.
+ * Source: none in the paper (resource release of this ABI). */
 void conv2d_serve_free(float **outputs, int n);
 
 /* ---------------------------------------------------------------- tuner */
@@ -360,7 +416,9 @@ typedef struct conv2d_tune_opts {
 typedef struct conv2d_tune_result {
     conv2d_config best;        /* the winner */
     double best_ms;            /* its sustained time per launch (re-timing) */
-    double default_ms;         /* median time of the default configuration (0 if not timed) */
+    double default_ms;         /* the default configuration's time in the winner's timing mode
+                                  (sustained re-timing when retime_reps > 0, else the sweep's
+                                  median); 0 if not timed. tuned/default = default_ms / best_ms */
     double median_ms;          /* time of the median-throughput configuration */
     double best_gflops, median_gflops, default_gflops;
     double impact;             /* best / median throughput of the sweep (the paper's tuning impact) */
@@ -374,9 +432,12 @@ typedef struct conv2d_tune_result {
     double top_ms[5];
     double compile_s, measure_s; /* wall time of the compile and measure phases */
     int evaluations;           /* configurations measured in this call (failures included) */
+    double best_sweep_ms;      /* the winner's time in the sweep (flushed single launches) */
+    double default_sweep_ms;   /* the default's time in the sweep (0 if not timed) */
 } conv2d_tune_result;
 
-/* Defaults for every option. */
+/* Defaults for every option.
+ * Source: none in the paper (option defaults). */
 void conv2d_tune_defaults(conv2d_tune_opts *opts);
 
 /* Compiles every legal point (in parallel on host threads), then for each:
@@ -387,20 +448,27 @@ void conv2d_tune_defaults(conv2d_tune_opts *opts);
  * together exceed the last-level cache); the winner is the lowest sustained
  * time, ties within tie_rel going to the smallest configuration tuple, and is
  * stored in the winners cache. Inputs are the seeded uniform recipe (input
- * seed 1, filter seed 2), on device. */
+ * seed 1, filter seed 2), on device.
+ * Source: Section 3 (compile, then time each configuration with events
+ * before and after the kernel; partial loop unrolling as a tunable);
+ * Section 4 (tuning impact: the optimum over the median, as in Table 3);
+ * Table 1 (the space). The local-search strategy is Section 4's premise
+ * that a local search walks the fitness flow graph (Eq. 1). */
 int conv2d_tune(conv2d_shape s, const conv2d_tune_opts *opts, conv2d_tune_result *res);
 
 /* Times one configuration the way the tuner does: seeded inputs on the
  * device, one verified launch (bitwise against the reference kernel), then
  * `warmup` untimed and `reps` timed launches (HIP events, optional cache flush
- * before each). Writes the median and minimum milliseconds. */
+ * before each). Writes the median and minimum milliseconds.
+ * Source: Section 3 (events recorded before and after the kernel). */
 int conv2d_benchmark(conv2d_shape s, const conv2d_config *cfg, int warmup, int reps, int flush_mall,
                      double *median_ms, double *min_ms);
 
 /* The same search with a caller-supplied cost instead of the GPU (a fake
  * backend for host tests): cost(cfg, user) returns a time in ms, or a
  * negative status to mark a compile (-3), launch (-4) or verify (-6)
- * failure. */
+ * failure.
+ * Source: as conv2d_tune (Sections 3-4), with the measurement replaced. */
 typedef double (*conv2d_cost_fn)(const conv2d_config *cfg, void *user);
 int conv2d_tune_synthetic(conv2d_shape s, conv2d_cost_fn cost, void *user,
                           const conv2d_tune_opts *opts, conv2d_tune_result *res);

@@ -63,30 +63,39 @@ typedef struct hotspot_plan_s *hotspot_plan_t;
 
 /* Hex hash of the hotspot kernel source built into this library (its code
  * without comments and blank runs; keys the hotspot winners cache and
- * results). Static storage, never NULL. */
+ * results). Static storage, never NULL.
+ * Source: none in the paper (the key of this library's stored tuning results). */
 const char *hotspot_kernel_hash(void);
 
-/* (32, 8, 1, 1, 1, 1, 1): one cell per thread, one step per launch. */
+/* (32, 8, 1, 1, 1, 1, 1): one cell per thread, one step per launch.
+ * Source: Section 4 takes the median as the untuned baseline; this fixed
+ * point of the Table 1 hotspot space is the library's second one. */
 void hotspot_default_config(hotspot_config *cfg);
 
 /* LDS bytes of a configuration: two buffers of the region with a one-cell
- * ring, 2 * (rows + 2) * ((cols + 2) | 1) floats. */
+ * ring, 2 * (rows + 2) * ((cols + 2) | 1) floats.
+ * Source: none in the paper (this kernel's layout; Table 1's block and tile
+ * sizes and temporal_tiling_factor set the region). */
 int hotspot_lds_bytes(const hotspot_config *cfg);
 
 /* CONV2D_OK if cfg is a legal point: every value on its axis, at most 1024
  * and at least 64 threads, a region of (block_y*tile_y) x (block_x*tile_x)
  * cells larger than twice `temporal` along both axes, LDS within lds_limit
- * (<= 0: 160 KiB). Else CONV2D_EINVAL with the reason. */
+ * (<= 0: 160 KiB). Else CONV2D_EINVAL with the reason.
+ * Source: Table 1 (the hotspot parameters); the paper does not print the
+ * restrictions. */
 int hotspot_config_check(hotspot_shape s, const hotspot_config *cfg, int lds_limit);
 
 /* The restricted space in enumeration order (block_x, block_y, tile_x,
  * tile_y, temporal, unroll_t, sh_power, each ascending). Writes up to cap
  * entries to out (may be NULL) and returns the number of legal points, or a
- * negative status. */
+ * negative status.
+ * Source: Table 1 (the hotspot's tunable parameters). */
 int hotspot_space(hotspot_shape s, int lds_limit, hotspot_config *out, int cap);
 
 /* Compiles a configuration for gfx950 with hiprtc (no GPU needed); the code
- * object's path goes to path_out (cap bytes). */
+ * object's path goes to path_out (cap bytes).
+ * Source: Section 3 (each configuration is compiled before it is benchmarked). */
 int hotspot_compile(const hotspot_config *cfg, char *path_out, int path_cap);
 
 /* --------------------------------------------------------------- plain path */
@@ -95,29 +104,37 @@ int hotspot_compile(const hotspot_config *cfg, char *path_out, int path_cap);
  * this grid size (tuned/hotspot_winners.jsonl beside the library, or
  * $HOTSPOT_WINNERS), else the winner for another grid that is legal here
  * (4096 x 4096 first, else the most recent), else the default. Compiles and
- * loads the kernel. */
+ * loads the kernel.
+ * Source: Section 5 (the hotspot benchmark kernel) with a point of the
+ * Table 1 space. */
 int hotspot_plan(hotspot_plan_t *plan, hotspot_shape s, const hotspot_config *cfg);
 
 /* The plan's configuration; *tuned = 1 when it is this grid's winner, 2
- * when it is another grid's, 0 otherwise (given or default). */
+ * when it is another grid's, 0 otherwise (given or default).
+ * Source: Table 1 (the parameters of the configuration). */
 int hotspot_plan_config(hotspot_plan_t plan, hotspot_config *cfg, int *tuned);
 
 /* d_out = the grid after `steps` (>= 0) steps from d_temp, on `stream`:
  * ceil(steps / temporal) launches that alternate between d_out and d_work, so
  * that the last writes d_out. d_work (rows*cols floats) may be NULL when one
  * launch suffices. d_temp and d_power are read only; d_out and d_work must
- * not overlap each other or the inputs. */
+ * not overlap each other or the inputs.
+ * Source: Section 5 (the hotspot kernel) and Section 6.2 (temporal tiling:
+ * several steps per launch, with redundant halo work); the update is the
+ * thermal model stated at the top of this header. */
 int hotspot_run(hotspot_plan_t plan, const float *d_temp, const float *d_power, float *d_out, float *d_work,
                 int steps, hotspot_coeffs k, void *stream);
 
 /* Frees the plan and unloads its code objects. It does not wait:
  * the caller first makes sure that no launch of the plan is queued or
  * running (synchronize the streams it ran on) and that no graph holding its
- * kernels is replayed afterwards. NULL is ignored. */
+ * kernels is replayed afterwards. NULL is ignored.
+ * Source: none in the paper (resource release of this ABI). */
 void hotspot_destroy(hotspot_plan_t plan);
 
 /* The same computation one step per launch, one cell per thread (the tuner's
- * bitwise reference). Buffers as for hotspot_run. */
+ * bitwise reference). Buffers as for hotspot_run.
+ * Source: Section 5 (the hotspot kernel's result without temporal tiling). */
 int hotspot_reference(hotspot_shape s, const float *d_temp, const float *d_power, float *d_out, float *d_work,
                       int steps, hotspot_coeffs k, void *stream);
 
@@ -138,7 +155,9 @@ typedef struct hotspot_tune_opts {
 
 typedef struct hotspot_tune_result {
     hotspot_config best;
-    double best_ms, default_ms, median_ms;       /* one hotspot_run of `steps` steps */
+    double best_ms, default_ms, median_ms;       /* one hotspot_run of `steps` steps; best_ms and
+                                                    default_ms in the re-timing's sustained mode
+                                                    (the sweep's when retime_reps = 0) */
     double best_gflops, median_gflops, default_gflops;
     double impact;                               /* best over median throughput (Section 4) */
     int n_space, n_illegal, n_compile_fail, n_launch_fail, n_verify_fail, n_timed, n_resumed;
@@ -146,8 +165,10 @@ typedef struct hotspot_tune_result {
     hotspot_config top[5];
     double top_ms[5];
     double compile_s, measure_s;
+    double best_sweep_ms, default_sweep_ms;      /* the sweep's flushed times (0 if not timed) */
 } hotspot_tune_result;
 
+/* Source: none in the paper (option defaults). */
 void hotspot_tune_defaults(hotspot_tune_opts *o);
 
 /* Sweeps the restricted space for grid s and `steps` steps per run (each
@@ -156,7 +177,10 @@ void hotspot_tune_defaults(hotspot_tune_opts *o);
  * re-times the ten fastest with sustained runs (as conv2d_tune), picks the
  * winner (lowest sustained time; ties within tie_rel to the smallest tuple)
  * and appends it to the winners cache. Throughput counts 14 floating-point
- * operations per cell and step. */
+ * operations per cell and step.
+ * Source: Section 3 (compile, then time each configuration with events);
+ * Section 4 (tuning impact, as in Table 3); Table 1 (the space); Table 5
+ * (the top configurations this reproduces on MI355X). */
 int hotspot_tune(hotspot_shape s, int steps, const hotspot_tune_opts *opts, hotspot_tune_result *res);
 
 #ifdef __cplusplus

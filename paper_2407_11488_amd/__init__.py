@@ -21,7 +21,7 @@ from ._binding import (CONV2D_EBUSY, CONV2D_ECOMPILE, CONV2D_EHIP, CONV2D_EINVAL
                        conv2d_version, lib, shape)
 from ._binding import (CONV2D_BATCH_BY_SIZE, CONV2D_BATCH_NO_GRAPH, CONV2D_BATCH_NO_PTR_CHECK, conv2d_batch_destroy,  # noqa: F401
                        conv2d_batch_info, conv2d_batch_plan, conv2d_batch_run, conv2d_batch_tune,
-                       conv2d_batch_tune_defaults, conv2d_compile_batch, conv2d_size_bucket)
+                       conv2d_batch_tune_defaults, conv2d_compile_batch, conv2d_size_bucket, conv2d_warm_cache)
 from ._binding import (REQUEST_DTYPE, ServeOpts, ServeReport, conv2d_serve, conv2d_serve_defaults,  # noqa: F401
                        conv2d_serve_free, requests_array)
 from ._binding import (HotspotCoeffs, HotspotConfig, HotspotShape, HotspotTuneOpts,  # noqa: F401

@@ -88,7 +88,8 @@ class TuneResult(ctypes.Structure):
                 ("impact", c_double), ("n_space", c_int), ("n_illegal", c_int), ("n_compile_fail", c_int),
                 ("n_launch_fail", c_int), ("n_verify_fail", c_int), ("n_timed", c_int), ("n_resumed", c_int),
                 ("default_rank", c_int), ("top", Config * 5), ("top_ms", c_double * 5),
-                ("compile_s", c_double), ("measure_s", c_double), ("evaluations", c_int)]
+                ("compile_s", c_double), ("measure_s", c_double), ("evaluations", c_int),
+                ("best_sweep_ms", c_double), ("default_sweep_ms", c_double)]
 
 
 COST_FN = ctypes.CFUNCTYPE(c_double, ctypes.POINTER(Config), c_void_p)
@@ -280,6 +281,7 @@ for _name, (_res, _args) in {
     "conv2d_batch_info": (c_int, [c_void_p, P(c_int), P(c_int), P(c_int), P(Config), P(c_int), c_int]),
     "conv2d_batch_destroy": (None, [c_void_p]),
     "conv2d_compile_batch": (c_int, [Shape, P(Config), c_char_p, c_int]),
+    "conv2d_warm_cache": (c_int, [c_char_p, c_int, P(c_int), P(c_int)]),
 }.items():
     _fn = getattr(lib, _name)
     _fn.restype, _fn.argtypes = _res, _args
@@ -365,6 +367,15 @@ def conv2d_batch_tune(shapes, opts: BatchTuneOpts | None = None) -> BatchTuneRes
 
 def conv2d_batch_destroy(batch: int) -> None:
     lib.conv2d_batch_destroy(batch)
+
+
+def conv2d_warm_cache(manifest: str, threads: int = 0):
+    """Compiles the manifest's programs missing from the code-object cache;
+    returns (compiled, already cached)."""
+    done, had = c_int(), c_int()
+    check(lib.conv2d_warm_cache(manifest.encode(), threads, ctypes.byref(done), ctypes.byref(had)),
+          "conv2d_warm_cache")
+    return done.value, had.value
 
 
 def conv2d_compile_batch(s: Shape, cfg) -> str:
@@ -475,7 +486,8 @@ class HotspotTuneResult(ctypes.Structure):
                 ("impact", c_double), ("n_space", c_int), ("n_illegal", c_int), ("n_compile_fail", c_int),
                 ("n_launch_fail", c_int), ("n_verify_fail", c_int), ("n_timed", c_int), ("n_resumed", c_int),
                 ("default_rank", c_int), ("top", HotspotConfig * 5), ("top_ms", c_double * 5),
-                ("compile_s", c_double), ("measure_s", c_double)]
+                ("compile_s", c_double), ("measure_s", c_double),
+                ("best_sweep_ms", c_double), ("default_sweep_ms", c_double)]
 
 
 _HS_SIGS = {

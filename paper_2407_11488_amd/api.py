@@ -85,13 +85,23 @@ _plans: dict = {}
 
 
 def conv2d(inp, filt, config=None, out=None, stream=None):
-    """One convolution; plans are cached per (shape, config)."""
+    """One convolution; plans are cached per (device, shape, config). A plan
+    whose filter goes to constant memory copies the filter into its module's
+    one constant array before each launch, so two streams must not share it:
+    such plans are cached per stream as well."""
     fh, fw = filt.shape
     H, W = inp.shape[0] - fh + 1, inp.shape[1] - fw + 1
     key = (_device(), H, W, fh, fw, None if config is None else tuple(B.config(config).tuple()))
+    st = _stream(stream)
     plan = _plans.get(key)
     if plan is None:
         plan = _plans[key] = Plan(H, W, fh, fw, config)
+        plan._first_stream = st
+    if plan.config[5] == 1 and plan._first_stream != st:
+        skey = key + (st,)
+        plan = _plans.get(skey)
+        if plan is None:
+            plan = _plans[skey] = Plan(H, W, fh, fw, _plans[key].config)
     return plan(inp, filt, out=out, stream=stream)
 
 

@@ -5,7 +5,13 @@ headers; device sources (*.hip) with hipcc for gfx950. Packed FP32
 instructions are disabled in every device compilation. Run it as a script
 (importing the package would load the library before it is built):
 
-    python paper_2407_11488_amd/build.py
+    python paper_2407_11488_amd/build.py [--warm]
+
+With --warm it then fills the run-time code-object cache (`_cache/` beside
+the library) with every program listed in `code_objects.txt` (the programs
+that the GPU tests, the smoke check and the benchmark load), compiling on
+the host's cores, so that those runs compile nothing on the GPU machine.
+Regenerate the list by running them with CONV2D_COMPILE_LOG=<file> set.
 """
 from __future__ import annotations
 
@@ -104,10 +110,36 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+MANIFEST = os.path.join(PKG, "code_objects.txt")
+
+
+def warm(manifest: str = MANIFEST, threads: int = 0, verbose: bool = False):
+    """Compiles every program of `manifest` that the code-object cache lacks
+    (conv2d_warm_cache, no GPU needed). Returns (compiled, already cached)."""
+    import ctypes
+    try:
+        import torch  # noqa: F401  (bind torch's HIP runtime, as the package does)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB)
+    lib.conv2d_last_error.restype = ctypes.c_char_p
+    lib.conv2d_warm_cache.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int)]
+    done, had = ctypes.c_int(), ctypes.c_int()
+    rc = lib.conv2d_warm_cache(manifest.encode(), threads, ctypes.byref(done), ctypes.byref(had))
+    if rc != 0:
+        raise RuntimeError(f"cache warm-up failed: {lib.conv2d_last_error().decode()}")
+    if verbose:
+        print(f"code-object cache: {done.value} compiled, {had.value} already present")
+    return done.value, had.value
+
+
 def clean():
     shutil.rmtree(BUILD, ignore_errors=True)
 
 
 if __name__ == "__main__":
     build(verbose=True)
+    if "--warm" in sys.argv[1:]:
+        warm(verbose=True)
     sys.exit(0)

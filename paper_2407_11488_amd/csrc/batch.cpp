@@ -686,7 +686,7 @@ extern "C" int conv2d_batch_tune(int n, const conv2d_shape* shapes, const conv2d
         if (rc) return rc;
         const std::vector<conv2d_config>& cand = cands[(size_t)g];
         std::vector<RecordT<conv2d_config>> timed;
-        double current_ms = 0;
+        double current_ms = -1;   // stays -1 when the current choice did not build or verify
         for (size_t k = 0; k < cand.size(); ++k) {
             conv2d_config c = cand[k];
             Module m;

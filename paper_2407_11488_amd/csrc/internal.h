@@ -74,6 +74,8 @@ int compile_direct(const conv2d_shape& s, const conv2d_config& c, int vin, int v
                    const std::string& arch, std::vector<char>* code, std::string* path,
                    bool batch = false);
 std::string code_cache_dir();
+// Kernel source text of the hotspot stencil (embedded at build).
+const std::string& hotspot_source();
 // Kernel symbol of one configuration, e.g. conv2d_direct_b16x16_t4x2_l1c0u1_f17x17.
 std::string direct_kernel_name(const conv2d_shape& s, const conv2d_config& c, bool batch = false);
 

@@ -2,8 +2,12 @@
 // an on-disk code-object cache, and module loading.
 #include <hip/hiprtc.h>
 
+#include <atomic>
 #include <cstdio>
+#include <fstream>
 #include <mutex>
+#include <set>
+#include <thread>
 
 #include "internal.h"
 
@@ -70,16 +74,43 @@ static std::string hiprtc_version_str()
     return std::to_string(maj) + "." + std::to_string(min);
 }
 
-int compile_program(const std::string& source, const char* name, const std::vector<std::string>& opts,
-                    const std::string& what, std::vector<char>* code, std::string* path)
+// The cache file of a program: keyed by the hash of its source, the
+// compiler version and its options.
+static std::string cache_file_for(const std::string& source, const char* name, const std::vector<std::string>& opts)
 {
     uint64_t h = fnv1a(source);
     h = fnv1a(hiprtc_version_str(), h);
     for (const auto& o : opts) h = fnv1a(o + "\x1f", h);
-    const std::string dir = code_cache_dir();
     std::string stem(name);
     stem = stem.substr(0, stem.find('.'));
-    const std::string file = dir + "/" + stem + "_" + hex64(h) + ".co";
+    return code_cache_dir() + "/" + stem + "_" + hex64(h) + ".co";
+}
+
+// With CONV2D_COMPILE_LOG set, every distinct program a process asks for
+// (hit or miss) is appended to that file as one line: the program's file
+// name, then its options, separated by single spaces. conv2d_warm_cache
+// replays such a list into the code-object cache.
+static void log_compile_request(const char* name, const std::vector<std::string>& opts)
+{
+    static const std::string log = env_str("CONV2D_COMPILE_LOG");
+    if (log.empty()) return;
+    std::string line(name);
+    for (const auto& o : opts) {
+        if (o.empty() || o.find_first_of(" \t\n") != std::string::npos) return;  // not representable
+        line += " " + o;
+    }
+    static std::mutex mu;
+    static std::set<std::string> seen;
+    std::lock_guard<std::mutex> lock(mu);
+    if (seen.insert(line).second) append_line(log, line);
+}
+
+int compile_program(const std::string& source, const char* name, const std::vector<std::string>& opts,
+                    const std::string& what, std::vector<char>* code, std::string* path)
+{
+    log_compile_request(name, opts);
+    const std::string dir = code_cache_dir();
+    const std::string file = cache_file_for(source, name, opts);
     if (path) *path = file;
     std::vector<char> cached;
     if (read_file(file, cached) && cached.size() > 64) {
@@ -169,3 +200,66 @@ void unload_module(Module* m)
 }
 
 }  // namespace conv2d
+
+extern "C" int conv2d_warm_cache(const char* manifest, int threads, int* n_compiled, int* n_cached)
+{
+    using namespace conv2d;
+    clear_error();
+    if (n_compiled) *n_compiled = 0;
+    if (n_cached) *n_cached = 0;
+    if (!manifest) return fail(CONV2D_EINVAL, "manifest is NULL");
+    std::ifstream in(manifest);
+    if (!in) return fail(CONV2D_EINVAL, std::string("cannot read ") + manifest);
+    struct Job {
+        std::string name;
+        std::vector<std::string> opts;
+    };
+    std::vector<Job> jobs;
+    std::set<std::string> seen;
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.empty() || line[0] == '#' || !seen.insert(line).second) continue;
+        Job j;
+        size_t p = 0;
+        while (p < line.size()) {
+            size_t q = line.find(' ', p);
+            if (q == std::string::npos) q = line.size();
+            if (q > p) (j.name.empty() ? j.name : (j.opts.push_back(""), j.opts.back())) = line.substr(p, q - p);
+            p = q + 1;
+        }
+        if (j.name != "conv2d_direct.hip" && j.name != "hotspot.hip")
+            return fail(CONV2D_EINVAL, "unknown program in manifest: " + j.name);
+        jobs.push_back(std::move(j));
+    }
+    if (threads <= 0) threads = (int)std::thread::hardware_concurrency();
+    threads = std::max(1, std::min(threads, 64));
+    std::atomic<size_t> next{0};
+    std::atomic<int> compiled{0}, cached{0}, failed{0};
+    std::mutex err_mu;
+    std::string first_err;
+    auto work = [&]() {
+        for (size_t k = next++; k < jobs.size(); k = next++) {
+            const Job& j = jobs[k];
+            const std::string& src = j.name == "hotspot.hip" ? hotspot_source() : direct_source();
+            std::vector<char> probe;
+            if (read_file(cache_file_for(src, j.name.c_str(), j.opts), probe) && probe.size() > 64) {
+                ++cached;
+                continue;
+            }
+            if (compile_program(src, j.name.c_str(), j.opts, "manifest entry", nullptr, nullptr) == CONV2D_OK) {
+                ++compiled;
+            } else {
+                ++failed;
+                std::lock_guard<std::mutex> lock(err_mu);
+                if (first_err.empty()) first_err = last_error_cstr();
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t) pool.emplace_back(work);
+    for (auto& t : pool) t.join();
+    if (n_compiled) *n_compiled = compiled;
+    if (n_cached) *n_cached = cached;
+    if (failed) return fail(CONV2D_ECOMPILE, std::to_string(failed.load()) + " manifest entries failed: " + first_err);
+    return CONV2D_OK;
+}

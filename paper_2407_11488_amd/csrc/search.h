@@ -126,4 +126,27 @@ int retime_and_pick(std::vector<RecordT<Cfg>>* eligible, MeasurerT<Cfg>* m, int 
     return CONV2D_OK;
 }
 
+// Times one configuration the way retime_and_pick times its candidates
+// (retime_reps sustained launches), so that a baseline such as the default
+// configuration can be compared with the winner in the same timing mode.
+// *r keeps the status of a failure; returns a non-zero status only for an
+// error of the measurer itself.
+template <class Cfg>
+int retime_one(const Cfg& c, MeasurerT<Cfg>* m, int warmup, int retime_reps, RecordT<Cfg>* r)
+{
+    std::vector<int> st;
+    double sec = 0;
+    int rc = m->prepare({c}, &st, &sec);
+    if (rc) return rc;
+    r->c = c;
+    if (st[0] != kOk) {
+        r->status = st[0];
+        return CONV2D_OK;
+    }
+    m->set_sustained(true);
+    rc = m->measure(c, warmup, retime_reps, 0, r);
+    m->set_sustained(false);
+    return rc;
+}
+
 }  // namespace conv2d

@@ -136,6 +136,11 @@ public:
         }
         for (auto& k : kernels_) unload_module(&k.mod);
         for (auto& kv : direct_) unload_module(&kv.second);
+        // Kept outputs belong to the caller only once run() has handed them
+        // over; after an error they are freed here (the streams are idle).
+        if (!outputs_handed_)
+            for (auto& r : req_)
+                if (o_.keep_outputs && r.out) hipFree(r.out);
     }
 
     int init()
@@ -228,6 +233,7 @@ public:
             if (lat_ms) lat_ms[i] = lat[i];
             if (outs) outs[i] = o_.keep_outputs ? req_[i].out : nullptr;
         }
+        outputs_handed_ = true;
         *rep = conv2d_serve_report{};
         rep->n_requests = n_;
         rep->n_batches = n_batches_;
@@ -251,25 +257,37 @@ public:
 
 private:
     // ---------------------------------------------------------------- memory
-    bool admit(int i)
+    // 1: admitted; 0: wait for in-flight requests to release budget or arena
+    // space; CONV2D_ENOMEM: it cannot be admitted by waiting (a kept output's
+    // own allocation failed, or the arena is empty and still has no room).
+    int admit(int i)
     {
         Req& r = req_[i];
-        if (in_flight_ + r.bytes > o_.hbm_budget) return false;
-        if (!arena_.alloc(r.bytes, &r.off)) return false;
+        if (in_flight_ + r.bytes > o_.hbm_budget) return in_flight_ ? 0 : no_room(i);
+        if (!arena_.alloc(r.bytes, &r.off)) return in_flight_ ? 0 : no_room(i);
         char* p = arena_.base() + r.off;
         r.in = reinterpret_cast<float*>(p);
         r.f = reinterpret_cast<float*>(p + align_up(r.n_in * 4));
         if (o_.keep_outputs) {
+            // Kept outputs live outside the arena until the caller frees them,
+            // so retiring requests cannot make room for this one.
             if (hipMalloc((void**)&r.out, std::max<size_t>(r.n_out * 4, 4)) != hipSuccess) {
+                (void)hipGetLastError();
+                r.out = nullptr;
                 arena_.release(r.off, r.bytes);
-                return false;
+                return fail(CONV2D_ENOMEM, "serve: output allocation of request " + std::to_string(i));
             }
         } else {
             r.out = reinterpret_cast<float*>(p + align_up(r.n_in * 4) + align_up(r.n_f * 4));
         }
         in_flight_ += r.bytes;
         peak_ = std::max(peak_, in_flight_);
-        return true;
+        return 1;
+    }
+
+    int no_room(int i)
+    {
+        return fail(CONV2D_ENOMEM, "serve: request " + std::to_string(i) + " does not fit the empty arena");
     }
 
     void retire(int i, double t)
@@ -370,7 +388,9 @@ private:
             }
             while (!pending.empty()) {
                 const int i = pending.front();
-                if (!admit(i)) {
+                const int a = admit(i);
+                if (a < 0) return a;
+                if (a == 0) {
                     if (!req_[i].stalled) { req_[i].stalled = true; ++stalled_; }
                     break;
                 }
@@ -449,7 +469,9 @@ private:
             const double wait = rq_[i].arrival_s - now();
             if (wait > 200e-6) std::this_thread::sleep_for(std::chrono::duration<double>(wait - 100e-6));
             while (now() < rq_[i].arrival_s) std::this_thread::yield();
-            if (!admit(i)) return fail(CONV2D_ENOMEM, "serve: arena fragmentation in the serial run");
+            const int a = admit(i);
+            if (a < 0) return a;
+            if (a == 0) return fail(CONV2D_ENOMEM, "serve: arena fragmentation in the serial run");
             Req& r = req_[i];
             r.t_launch = now();
             fill[0] = FillDesc{r.in, r.n_in, rq_[i].seed_in, 0};
@@ -489,6 +511,7 @@ private:
     size_t in_flight_ = 0, peak_ = 0;
     int done_ = 0, n_batches_ = 0, stalled_ = 0;
     double late_start_ = 0;
+    bool outputs_handed_ = false;
 };
 
 }  // namespace

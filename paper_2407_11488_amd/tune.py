@@ -61,7 +61,11 @@ def report(shape, r) -> dict:
         "impact": round(r.impact, 3),
         "default_ms": round(r.default_ms, 5),
         "default_gflops": round(r.default_gflops, 1),
+        # both in the sustained re-timing's mode; the sweep-mode ratio beside it
         "tuned_vs_default": round(r.default_ms / r.best_ms, 3) if r.default_ms > 0 else None,
+        "best_sweep_ms": round(r.best_sweep_ms, 5), "default_sweep_ms": round(r.default_sweep_ms, 5),
+        "tuned_vs_default_sweep": (round(r.default_sweep_ms / r.best_sweep_ms, 3)
+                                   if r.default_sweep_ms > 0 and r.best_sweep_ms > 0 else None),
         "default_rank": r.default_rank,
         "n_space": r.n_space, "n_illegal": r.n_illegal, "n_timed": r.n_timed,
         "n_compile_fail": r.n_compile_fail, "n_launch_fail": r.n_launch_fail,
@@ -105,7 +109,11 @@ def tune_hotspot(rows, cols, steps, a, results_path):
         "winner": list(r.best.tuple()), "best_ms": round(r.best_ms, 5), "best_gflops": round(r.best_gflops, 1),
         "median_gflops": round(r.median_gflops, 1), "impact": round(r.impact, 3),
         "default_ms": round(r.default_ms, 5), "default_gflops": round(r.default_gflops, 1),
+        # both in the sustained re-timing's mode; the sweep-mode ratio beside it
         "tuned_vs_default": round(r.default_ms / r.best_ms, 3) if r.default_ms > 0 else None,
+        "best_sweep_ms": round(r.best_sweep_ms, 5), "default_sweep_ms": round(r.default_sweep_ms, 5),
+        "tuned_vs_default_sweep": (round(r.default_sweep_ms / r.best_sweep_ms, 3)
+                                   if r.default_sweep_ms > 0 and r.best_sweep_ms > 0 else None),
         "default_rank": r.default_rank, "n_space": r.n_space, "n_illegal": r.n_illegal, "n_timed": r.n_timed,
         "n_compile_fail": r.n_compile_fail, "n_launch_fail": r.n_launch_fail, "n_verify_fail": r.n_verify_fail,
         "n_resumed": r.n_resumed, "compile_s": round(r.compile_s, 1), "measure_s": round(r.measure_s, 1),

@@ -103,6 +103,33 @@ def test_plan_shared_by_threads_on_their_own_streams():
     plan.close()
 
 
+def test_conv2d_helper_constant_filter_on_two_streams():
+    """conv2d() with a configuration whose filter goes to constant memory,
+    called on two streams with different filters and no synchronisation
+    between the calls: each stream gets a plan (and a constant array) of its
+    own, so each output equals a single-stream run bit for bit."""
+    torch = torch_cuda()
+    H, W, fh, fw = 256, 320, 9, 9
+    cfg = (16, 16, 1, 1, 1, 1, 1)                 # the default: LDS, filter in constant memory
+    data = [datagen.conv_problem(H, W, fh, fw, seed_in=110 + k, seed_f=120 + k) for k in range(2)]
+    dev = [(to_dev(inp), to_dev(f)) for inp, f in data]
+    want = []
+    for di, df in dev:
+        want.append(C.conv2d(di, df, config=cfg).cpu().numpy().copy())
+        torch.cuda.synchronize()
+    assert not np.array_equal(want[0], want[1])
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.full((H, W), float("nan"), device="cuda") for _ in range(2)]
+    torch.cuda.synchronize()
+    say("conv2d() constant-filter plan on two streams")
+    for _ in range(20):
+        for k in range(2):
+            C.conv2d(dev[k][0], dev[k][1], config=cfg, out=outs[k], stream=streams[k])
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert np.array_equal(outs[k].cpu().numpy().view(np.uint32), want[k].view(np.uint32)), k
+
+
 def test_close_waits_for_queued_work_and_keeps_a_captured_plan():
     """A plan dropped right after an asynchronous call (a temporary object)
     frees its code only after the device has finished the queued work: the

@@ -144,3 +144,36 @@ def test_serve_argument_errors():
     o.streams = 0
     with pytest.raises(C.Conv2dError):
         C.conv2d_serve(reqs, o)
+
+
+def test_kept_output_allocation_failure_is_reported():
+    """With keep_outputs, a request whose own output allocation fails (the
+    device is full: a blocker tensor leaves less free memory than the output
+    needs) makes conv2d_serve return CONV2D_ENOMEM instead of waiting for
+    memory that retiring requests cannot free; the outputs it had allocated
+    are released (the free memory afterwards is what it was before)."""
+    torch = torch_cuda()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, _ = torch.cuda.mem_get_info()
+    H = W = 16384                                   # 1 GiB output, 1.07 GB input
+    first = (256, 256, 3, 3)
+    reqs = C.requests_array([0.0, 0.0], [first, (H, W, 3, 3)], [1, 2], [3, 4])
+    o = C.conv2d_serve_defaults()
+    o.hbm_budget = 4 * (H + 2) * (W + 2) + (64 << 20)
+    o.streams = 1
+    leave = o.hbm_budget + (512 << 20)               # the arena fits, a 1 GiB output does not
+    blocker = torch.empty(max(free0 - leave, 0) // 4, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    say(f"kept-output allocation failure: blocker {blocker.numel() * 4 / 2**30:.1f} GiB")
+    try:
+        with pytest.raises(C.Conv2dError) as e:
+            C.conv2d_serve(reqs, o, keep_outputs=True)
+        assert e.value.status == C.CONV2D_ENOMEM
+        assert "output allocation" in str(e.value)
+    finally:
+        del blocker
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 >= free0 - (64 << 20), (free0, free1)
