@@ -4,8 +4,12 @@
 One step = one conv2d_run of the tuned configuration over the whole image,
 inputs resident in HBM. Prints one JSON line with the throughput (GFLOP/s,
 2*H*W*fh*fw per step), the roofline position of the kernel (FP32 vector ALU
-bound), the tuned/default speedup, and the FP64 CPU oracle timed on this
-host as a baseline.
+bound), the tuned/default speedup, the parity of the timed output (bit for
+bit against the reference kernel on the device; against the FP64 oracle over
+every output in the CPU-baseline leg), the filter-size sweep (each filter's
+winner and the 17x17 winner applied unchanged), the batched, served and
+hotspot workloads, and the FP64 CPU oracle timed on this host as a baseline.
+A timed output that fails parity prints no headline value and exits 1.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -32,11 +36,15 @@ def parse():
     # (some 150 launches) brings it to the steady state that the timed steps
     # are meant to measure.
     ap.add_argument("--warmup", type=int, default=150)
-    ap.add_argument("--default-steps", type=int, default=20)
+    # The default configuration is timed first, over ~50 ms of launches.
+    ap.add_argument("--default-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="duration of the serving trace (batched and serial each); 0 skips serving")
+    ap.add_argument("--no-filter-sweep", action="store_true",
+                    help="skip the filter-size sweep (4096x4096, filters 3..31, tuned winners and the "
+                         "17x17 winner applied unchanged)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-hotspot", action="store_true",
                     help="skip the hotspot stencil summary (4096x4096 chip workload, 60 steps)")
@@ -104,15 +112,24 @@ def _time_oracle(oracle, inp, f, seconds: float, max_runs: int):
             return runs, el
 
 
-def cpu_baseline(seconds: float):
+def cpu_baseline(seconds: float, gpu_out=None):
     """The FP64 oracle on the same 4096x4096 / 17x17 problem with all host
     threads, repeated until about `seconds` have passed; and, single-threaded,
-    on the 1024x1024 / 17x17 plain workload (zero halo) for a few seconds."""
+    on the 1024x1024 / 17x17 plain workload (zero halo) for a few seconds.
+    With gpu_out (the timed plan's last output, on the host), the oracle's
+    whole output (with the per-point denominators S) is first compared with
+    it: the worst per-point normalised error over all outputs."""
     import datagen
     import oracle
     threads = oracle.num_threads()
     inp, f = datagen.conv_problem(H, W, FH, FW)
     flops = 2.0 * H * W * FH * FW
+    parity = None
+    if gpu_out is not None:
+        ref, s = oracle.conv2d_f64(inp, f, with_abs=True)
+        parity = {"outputs_compared": int(gpu_out.size),
+                  "max_normalized_error": oracle.normalized_error(gpu_out.reshape(H, W), ref, s)}
+        del ref, s
     runs, el = _time_oracle(oracle, inp, f, seconds, 50)
     out = {"value": round(flops * runs / el / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
            "sample": f"the whole 4096x4096/17x17 problem (FP64, OpenMP over rows), {runs} run(s), {el:.1f} s",
@@ -125,7 +142,7 @@ def cpu_baseline(seconds: float):
         oracle.set_num_threads(threads)
     out["single_thread_1024x1024"] = {"value": round(2.0 * 1024 * 1024 * FH * FW * r1 / e1 / 1e9, 3),
                                       "unit": "GFLOP/s", "cores": 1, "runs": r1, "seconds": round(e1, 2)}
-    return out
+    return out, parity
 
 
 def main():
@@ -158,6 +175,16 @@ def main():
     ms, wall = time_plan(torch, C, plan, d_in, d_f, d_out, args.steps, args.warmup, stream)
     gflops = flops / (ms * 1e-3) / 1e9
     achieved_tflops = gflops / 1e3
+
+    # Parity of the timed output: the reference kernel (one thread per output,
+    # the same accumulation order) on the same buffers must give the same bits.
+    ref_out = torch.empty_like(d_out)
+    C.conv2d_reference(C.shape(H, W, FH, FW), d_in.data_ptr(), d_f.data_ptr(), ref_out.data_ptr(),
+                       stream.cuda_stream)
+    torch.cuda.synchronize()
+    mismatches = int((d_out.view(torch.int32) != ref_out.view(torch.int32)).sum().item())
+    gpu_out = d_out.cpu().numpy()
+    del ref_out
 
     traffic, traffic_src = measured_traffic(C, plan)
     kname = "conv2d_direct_b{}x{}_t{}x{}_l{}c{}u{}_f{}x{}".format(*plan.config, FH, FW)
@@ -196,6 +223,8 @@ def main():
         "default_config": list(dplan.config),
         "wall_ms_per_step": round(1e3 * wall / args.steps, 5),
         "roofline": roofline,
+        "parity": {"mismatches_vs_reference_kernel": mismatches, "outputs": H * W,
+                   "tolerance": "max |gpu - oracle| / sum |f||in| <= 1e-5 per output"},
     }
     plan.close()
     dplan.close()
@@ -211,6 +240,8 @@ def main():
     torch.cuda.empty_cache()
     from paper_2407_11488_amd import workloads
     line["plain_1024"] = workloads.plain_benchmark()
+    if not args.no_filter_sweep:
+        line["filter_sweep"] = workloads.filter_sweep_benchmark()
     if not args.no_batch:
         line["batch"] = workloads.batch_benchmark(reps=20)
     if not args.no_hotspot:
@@ -228,9 +259,15 @@ def main():
                            "serial_p50_ms": run["serial"]["p50_ms"], "serial_p99_ms": run["serial"]["p99_ms"],
                            "serial_req_per_s": run["serial"]["req_per_s"]}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        line["cpu_baseline"], oracle_parity = cpu_baseline(args.cpu_seconds, gpu_out)
+        line["parity"].update(oracle_parity)
+    ok = mismatches == 0 and line["parity"].get("max_normalized_error", 0.0) <= 1e-5
+    if not ok:
+        # No headline for an output that fails parity.
+        line["parity_failed"] = True
+        line["value"] = None
     print(json.dumps(line), flush=True)
-    return 0
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":

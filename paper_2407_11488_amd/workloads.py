@@ -20,6 +20,13 @@ default configuration.
 
     python -m paper_2407_11488_amd.workloads hotspot [--reps 20] [--steps 60]
 
+sweep: the filter-size sweep at 4096 x 4096 (filters 3 to 31), each
+filter's tuned plan and the 17 x 17 winner applied unchanged, timed over
+back-to-back launches that cycle through input copies larger together than
+the last-level cache.
+
+    python -m paper_2407_11488_amd.workloads sweep [--reps 60] [--filters 3 7]
+
 plain (bench.py only): the 1024 x 1024 / 17 x 17 workload with a zero input
 ring in the default configuration.
 
@@ -136,6 +143,79 @@ def batch_benchmark(reps: int = 20, warmup: int = 3, n: int = 64) -> dict:
     for p in plans:
         p.close()
     return res
+
+
+SWEEP_FILTERS = (3, 5, 7, 9, 15, 17, 31)
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
+
+
+def filter_sweep_benchmark(filters=SWEEP_FILTERS, hw: int = 4096, reps: int = 60, copies: int = 4,
+                           ref_filter: int = 17) -> dict:
+    """The filter-size sweep at hw x hw: each filter's tuned plan (winners
+    cache) and the ref_filter x ref_filter winner applied unchanged, timed
+    back to back over `copies` input/output pairs that together exceed the
+    256 MB last-level cache (each launch reads its input from HBM). Reports
+    ms, TFLOP/s and algorithmic GB/s per filter, the reference winner's
+    application efficiency e_i = P(x) / max P (Eq. 3, over filter shapes
+    instead of devices) and its performance portability over the shapes
+    (Eq. 2, the harmonic mean of the e_i)."""
+    torch = _torch()
+    from .api import Plan
+    st = torch.cuda.current_stream()
+    ref_cfg = tuned_config_for_filter(ref_filter, ref_filter)
+    rows = []
+    for fsz in filters:
+        shape = (hw, hw, fsz, fsz)
+        n_in, n_out = (hw + fsz - 1) ** 2, hw * hw
+        ins = [torch.empty(n_in, dtype=torch.float32, device="cuda") for _ in range(copies)]
+        outs = [torch.empty(n_out, dtype=torch.float32, device="cuda") for _ in range(copies)]
+        filt = torch.empty(fsz * fsz, dtype=torch.float32, device="cuda")
+        for x in ins:
+            B.conv2d_fill_uniform(x.data_ptr(), n_in, datagen.SEED_INPUT, 0, st.cuda_stream)
+        B.conv2d_fill_uniform(filt.data_ptr(), fsz * fsz, datagen.SEED_FILTER, 0, st.cuda_stream)
+        own = Plan(*shape)
+        other = Plan(*shape, config=ref_cfg)
+        timings = {}
+        for name, plan in (("own", own), ("ref", other)):
+            args = [(plan.handle, ins[k].data_ptr(), filt.data_ptr(), outs[k].data_ptr()) for k in range(copies)]
+            run, sp = B.lib.conv2d_run, st.cuda_stream
+
+            def launch_all(args=args, run=run, sp=sp):
+                for (h, x, f, y) in args:
+                    rc = run(h, x, f, y, sp)
+                    if rc:
+                        raise B.Conv2dError(rc, "conv2d_run")
+
+            warm_up(launch_all, st, at_least=2)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            k_rounds = max(1, reps // copies)
+            e0.record(st)
+            for _ in range(k_rounds):
+                launch_all()
+            e1.record(st)
+            torch.cuda.synchronize()
+            timings[name] = e0.elapsed_time(e1) / (k_rounds * copies)
+        fl, by = analysis.flops(shape), analysis.algorithmic_bytes(shape)
+        ms, ms_ref = timings["own"], timings["ref"]
+        best = min(ms, ms_ref)
+        rows.append({"filter": fsz, "config": list(own.config), "source": own.source, "ms": round(ms, 5),
+                     "tflops": round(fl / (ms * 1e-3) / 1e12, 2), "gbs": round(by / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(by / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 3),
+                     "frac_fp32_unpacked": round(fl / (ms * 1e-3) / 1e12 / PEAK_FP32_UNPACKED_TFLOPS, 3),
+                     f"winner{ref_filter}_ms": round(ms_ref, 5),
+                     f"e_winner{ref_filter}": round(best / ms_ref, 3)})
+        own.close()
+        other.close()
+        del ins, outs, filt
+        torch.cuda.empty_cache()
+    effs = [r[f"e_winner{ref_filter}"] for r in rows]
+    return {"workload": f"out {hw}x{hw}, filters " + ", ".join(f"{f}x{f}" for f in filters) +
+                        ", input and filter uniform [-1,1) (seeds 1, 2)",
+            "timing": f"HIP events over back-to-back launches cycling {copies} input/output copies "
+                      f"(inputs read from HBM, not the last-level cache)",
+            f"winner{ref_filter}": list(ref_cfg), "filters": rows,
+            f"pp_winner{ref_filter}": round(len(effs) / sum(1.0 / e for e in effs), 3)}
 
 
 def plain_benchmark(reps: int = 100, out_hw: int = 1024, f: int = 17) -> dict:
@@ -329,9 +409,15 @@ def main(argv=None) -> int:
     h = sub.add_parser("hotspot")
     h.add_argument("--reps", type=int, default=20)
     h.add_argument("--steps", type=int, default=60)
+    w = sub.add_parser("sweep", help="the filter-size sweep at 4096 x 4096 (tuned winners and the 17x17 "
+                                     "winner applied unchanged)")
+    w.add_argument("--reps", type=int, default=60)
+    w.add_argument("--filters", type=int, nargs="*", default=list(SWEEP_FILTERS))
     a = ap.parse_args(argv)
     if a.cmd == "batch":
         print(json.dumps(batch_benchmark(a.reps)), flush=True)
+    elif a.cmd == "sweep":
+        print(json.dumps(filter_sweep_benchmark(tuple(a.filters), reps=a.reps)), flush=True)
     elif a.cmd == "hotspot":
         print(json.dumps(hotspot_benchmark(a.reps, steps=a.steps)), flush=True)
     else:

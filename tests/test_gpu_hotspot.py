@@ -28,6 +28,18 @@ def bound(temp, power, steps, k):
     return 8.0 * max(steps, 1) * 2.0 ** -24 * m
 
 
+def stored_winners():
+    """The configurations of the hotspot winners cache shipped with the
+    library (one per tuned grid)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(C.LIB_PATH), "tuned", "hotspot_winners.jsonl")
+    with open(path) as fh:
+        cfgs = {tuple(json.loads(line)["config"]) for line in fh if line.strip()}
+    assert cfgs
+    return sorted(cfgs)
+
+
 def _run_plan(cfg, temp_d, power_d, steps, k, rows, cols):
     torch = torch_cuda()
     plan = C.Hotspot(rows, cols, cfg)
@@ -55,13 +67,15 @@ def test_reference_matches_oracle(rows, cols, steps):
 
 def test_stratified_configs_bitwise():
     """About 130 points of the space (every 16th in enumeration order, plus the
-    default and the extremes of each axis) on a ragged 181 x 97 grid, 13 steps
-    (partial last launches for most temporal factors): every point equals the
-    reference bit for bit."""
+    default, the stored winners of every tuned grid and the extremes of each
+    axis) on a ragged 181 x 97 grid, 13 steps (partial last launches for most
+    temporal factors): every point equals the reference bit for bit. The
+    stress coefficients make every term of the step larger than the error
+    bound, so a point that dropped one would fail."""
     torch = torch_cuda()
     rows, cols, steps = 181, 97, 13
     space = C.hotspot_space(C.hotspot_shape(rows, cols))
-    pick = space[::16] + [C.hotspot_default_config().tuple()]
+    pick = space[::16] + [C.hotspot_default_config().tuple()] + stored_winners()
     for ax in range(7):
         vals = sorted({c[ax] for c in space})
         for v in (vals[0], vals[-1]):
@@ -84,22 +98,56 @@ def test_stratified_configs_bitwise():
 
 def test_chip_workload_full_size():
     """4096 x 4096 chip workload, 60 steps, in the configuration the plan picks
-    (the tuned winner when cached): every cell within the bound of the FP64
-    oracle."""
+    (the tuned winner when cached, the one the benchmark times): bit for bit
+    equal to the one-step reference kernel, and every cell within the bound
+    of the FP64 oracle."""
     torch = torch_cuda()
     rows = cols = 4096
     steps = 60
     temp, power, k = datagen.hotspot_problem(rows, cols)
     plan = C.Hotspot(rows, cols)
     say(f"hotspot 4096 with {plan.source} config {plan.config}")
-    out = plan(to_dev(temp), to_dev(power), steps, k)
+    td, pd = to_dev(temp), to_dev(power)
+    out = plan(td, pd, steps, k)
+    ref_dev = C.reference_hotspot(td, pd, steps, k)
     torch.cuda.synchronize()
-    got = out.cpu().numpy()
     plan.close()
+    mism = int((out.view(torch.int32) != ref_dev.view(torch.int32)).sum().item())
+    assert mism == 0, f"{mism} cells differ from the reference kernel"
+    got = out.cpu().numpy()
     ref = oracle.hotspot_f64(temp, power, steps, *k)
     err = float(np.max(np.abs(got - ref)))
     say(f"hotspot 4096 max error {err:.3e} K (bound {bound(temp, power, steps, k):.3e})")
     assert err <= bound(temp, power, steps, k)
+
+
+def test_full_size_every_term_visible():
+    """4096 x 4096, 60 steps, in the plan's (tuned) configuration, with the
+    stress coefficients on uniform [-1, 1) temperatures and powers: dropping
+    the power term or the vertical sink from the oracle moves its result by
+    far more than the FP32 bound, so a kernel that lost either term fails;
+    the plan's result is within the bound of the oracle."""
+    torch = torch_cuda()
+    rows = cols = 4096
+    steps = 60
+    temp = datagen.uniform_pm1(91, rows * cols).reshape(rows, cols)
+    power = datagen.uniform_pm1(92, rows * cols).reshape(rows, cols)
+    plan = C.Hotspot(rows, cols)
+    say(f"hotspot 4096 stress coefficients with {plan.source} config {plan.config}")
+    out = plan(to_dev(temp), to_dev(power), steps, STRESS)
+    torch.cuda.synchronize()
+    plan.close()
+    got = out.cpu().numpy()
+    b = bound(temp, power, steps, STRESS)
+    ref = oracle.hotspot_f64(temp, power, steps, *STRESS)
+    no_power = oracle.hotspot_f64(temp, power * 0, steps, *STRESS)
+    cc, gx, gy, _, t_amb = STRESS
+    no_sink = oracle.hotspot_f64(temp, power, steps, cc, gx, gy, 0.0, t_amb)
+    assert np.max(np.abs(ref - no_power)) > 100 * b
+    assert np.max(np.abs(ref - no_sink)) > 100 * b
+    err = float(np.max(np.abs(got - ref)))
+    say(f"hotspot 4096 stress max error {err:.3e} (bound {b:.3e})")
+    assert err <= b
 
 
 def test_edge_cases():
