@@ -395,6 +395,20 @@ def hotspot_benchmark(reps: int = 20, warmup: int = 3, steps: int = 60, rows: in
     return res
 
 
+def calibration_copy(mib: int, reps: int = 3) -> dict:
+    """Negates `mib` MiB with torch `reps` times (each reads and writes mib
+    MiB): a kernel of known traffic beside the profiled ones, so that the
+    profiler's FETCH_SIZE / WRITE_SIZE can be scaled to bytes."""
+    torch = _torch()
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    return {"calibration": "torch.neg elementwise", "read_bytes": n * 4, "write_bytes": n * 4, "launches": reps}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -413,6 +427,10 @@ def main(argv=None) -> int:
                                      "winner applied unchanged)")
     w.add_argument("--reps", type=int, default=60)
     w.add_argument("--filters", type=int, nargs="*", default=list(SWEEP_FILTERS))
+    for sp in (w, h):
+        sp.add_argument("--calib-copy-mib", type=int, default=0,
+                        help="afterwards, negate this many MiB with torch (a plain elementwise kernel of "
+                             "known traffic: calibration of the profiler's byte counters)")
     a = ap.parse_args(argv)
     if a.cmd == "batch":
         print(json.dumps(batch_benchmark(a.reps)), flush=True)
@@ -423,6 +441,8 @@ def main(argv=None) -> int:
     else:
         print(json.dumps(serve_benchmark(a.duration, tuple(a.rates), a.budget_gib, a.streams, a.max_batch)),
               flush=True)
+    if getattr(a, "calib_copy_mib", 0) > 0:
+        print(json.dumps(calibration_copy(a.calib_copy_mib)), flush=True)
     return 0
 
 
