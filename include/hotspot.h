@@ -125,6 +125,25 @@ int hotspot_plan_config(hotspot_plan_t plan, hotspot_config *cfg, int *tuned);
 int hotspot_run(hotspot_plan_t plan, const float *d_temp, const float *d_power, float *d_out, float *d_work,
                 int steps, hotspot_coeffs k, void *stream);
 
+/* Cells of the fixed work grid of hotspot_run_noalloc (64 MiB of FP32). */
+#define HOTSPOT_NOALLOC_CELLS (4096 * 4096)
+
+/* hotspot_run without a work buffer and without any allocation, for callers
+ * that cannot allocate device memory (code under graph capture, serving
+ * loops or harnesses that forbid hipMalloc). A run of more than one launch
+ * alternates between d_out and a fixed work grid of the library's own device
+ * code (HOTSPOT_NOALLOC_CELLS floats on every GPU the library runs on, kept
+ * until the process ends); grids of more cells need more than one launch
+ * only when steps > temporal, and then return CONV2D_EINVAL. The results are
+ * those of hotspot_run, bit for bit. Every call on one GPU uses that GPU's
+ * one work grid: calls that overlap on a GPU (other streams or host
+ * threads) race, so the caller orders them. The grid's contents are not
+ * kept from call to call (every launch overwrites what it reads later).
+ * Source: none in the paper (the variant of hotspot_run for callers that
+ * cannot allocate). */
+int hotspot_run_noalloc(hotspot_plan_t plan, const float *d_temp, const float *d_power, float *d_out, int steps,
+                        hotspot_coeffs k, void *stream);
+
 /* Frees the plan and unloads its code objects. It does not wait:
  * the caller first makes sure that no launch of the plan is queued or
  * running (synchronize the streams it ran on) and that no graph holding its

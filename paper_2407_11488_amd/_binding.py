@@ -499,6 +499,7 @@ _HS_SIGS = {
     "hotspot_plan": (c_int, [P(c_void_p), HotspotShape, P(HotspotConfig)]),
     "hotspot_plan_config": (c_int, [c_void_p, P(HotspotConfig), P(c_int)]),
     "hotspot_run": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, HotspotCoeffs, c_void_p]),
+    "hotspot_run_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, HotspotCoeffs, c_void_p]),
     "hotspot_destroy": (None, [c_void_p]),
     "hotspot_reference": (c_int, [HotspotShape, c_void_p, c_void_p, c_void_p, c_void_p, c_int, HotspotCoeffs,
                                   c_void_p]),
@@ -567,6 +568,15 @@ def hotspot_plan_config(plan: int):
 def hotspot_run(plan: int, d_temp: int, d_power: int, d_out: int, d_work, steps: int, k: HotspotCoeffs,
                 stream: int = 0) -> None:
     check(lib.hotspot_run(plan, d_temp, d_power, d_out, d_work, int(steps), k, stream), "hotspot_run")
+
+
+HOTSPOT_NOALLOC_CELLS = 4096 * 4096
+
+
+def hotspot_run_noalloc(plan: int, d_temp: int, d_power: int, d_out: int, steps: int, k: HotspotCoeffs,
+                        stream: int = 0) -> None:
+    """hotspot_run with the library's fixed work grid: allocates nothing."""
+    check(lib.hotspot_run_noalloc(plan, d_temp, d_power, d_out, int(steps), k, stream), "hotspot_run_noalloc")
 
 
 def hotspot_destroy(plan: int) -> None:

@@ -676,6 +676,31 @@ extern "C" int hotspot_run(hotspot_plan_t plan, const float* d_temp, const float
                   static_cast<hipStream_t>(stream));
 }
 
+namespace conv2d {
+// hotspot_run with a work grid the caller vouches for (work_cells floats of
+// device memory that overlaps none of the caller's buffers): the library's
+// fixed work array of hotspot_run_noalloc. Allocates nothing.
+int hotspot_run_fixed_work(hotspot_plan_t plan, const float* d_temp, const float* d_power, float* d_out,
+                           float* work, size_t work_cells, int steps, hotspot_coeffs k, void* stream)
+{
+    if (!plan) return fail(CONV2D_EINVAL, "plan is NULL");
+    if (steps < 0) return fail(CONV2D_EINVAL, "steps must be >= 0");
+    int dev = -1;
+    CONV2D_HIP(hipGetDevice(&dev));
+    if (dev != plan->device) return fail(CONV2D_EINVAL, "plan was made for another device");
+    const int launches = steps == 0 ? 0 : (steps + plan->cfg.temporal - 1) / plan->cfg.temporal;
+    const size_t cells = (size_t)plan->shape.rows * (size_t)plan->shape.cols;
+    if (launches > 1 && cells > work_cells)
+        return fail(CONV2D_EINVAL, "grid of " + std::to_string(cells) + " cells exceeds the fixed work array of " +
+                                       std::to_string(work_cells));
+    // The caller's buffers as for one launch; the work array is the library's own.
+    int rc = check_buffers(plan->shape, d_temp, d_power, d_out, nullptr, std::min(launches, 1));
+    if (rc) return rc;
+    return hs_run(plan->mod, plan->cfg, plan->shape, d_temp, d_power, d_out, work, steps, k,
+                  static_cast<hipStream_t>(stream));
+}
+}  // namespace conv2d
+
 extern "C" void hotspot_destroy(hotspot_plan_t plan)
 {
     if (!plan) return;

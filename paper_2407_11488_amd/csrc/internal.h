@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "conv2d.h"
+#include "hotspot.h"
 
 namespace conv2d {
 
@@ -169,6 +170,11 @@ struct FillDesc {
 };
 static_assert(sizeof(FillDesc) == 32, "fill descriptor layout");
 int launch_fill_uniform_batch(const FillDesc* d_desc, int n_desc, unsigned long long max_n, hipStream_t st);
+
+// ---------------------------------------------------------------- hotspot
+// hotspot_run with the library's fixed work array (see hotspot_noalloc.hip).
+int hotspot_run_fixed_work(hotspot_plan_s* plan, const float* d_temp, const float* d_power, float* d_out,
+                           float* work, size_t work_cells, int steps, hotspot_coeffs k, void* stream);
 
 // ---------------------------------------------------------------- JSON lines
 // Minimal flat-object JSON: string, number and number-array values.
