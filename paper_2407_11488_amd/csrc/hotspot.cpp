@@ -541,8 +541,12 @@ extern "C" void hotspot_default_config(hotspot_config* cfg)
 extern "C" int hotspot_lds_bytes(const hotspot_config* cfg)
 {
     if (!cfg) return fail(CONV2D_EINVAL, "cfg is NULL");
-    // two buffers of the region plus a one-cell ring, odd pitch
-    const long long b = 2ll * (region_rows(*cfg) + 2) * ((region_cols(*cfg) + 2) | 1) * 4;
+    // block_x <= 64: two buffers of the thread rows' top and bottom cell rows
+    // (two zero rows beside them); wider blocks: two buffers of the region
+    // plus a one-cell ring, odd pitch
+    const long long b = cfg->block_x <= 64
+                            ? 2ll * (2 * cfg->block_y + 4) * region_cols(*cfg) * 4
+                            : 2ll * (region_rows(*cfg) + 2) * ((region_cols(*cfg) + 2) | 1) * 4;
     return b > INT_MAX ? INT_MAX : (int)b;
 }
 

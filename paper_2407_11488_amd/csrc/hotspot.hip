@@ -24,9 +24,16 @@
 // Design (MI355X): a workgroup owns a region of (BY*TY) x (BX*TX) cells, its
 // output tile plus a halo of TT cells on every side; neighbouring regions
 // overlap by 2*TT. Each thread keeps its TY x TX cells in VGPRs through all
-// steps. Per step it publishes them to one of two LDS buffers (each with a
-// zero ring around the region), waits once, and reads from LDS only the ring
-// of neighbours that belong to other threads.
+// steps, and per step exchanges its edge cells with the neighbouring threads
+// through one of two LDS buffers (used alternately, so one barrier per step):
+//  * BX <= 64 (a wave holds whole thread rows): horizontal neighbours come
+//    straight from the adjacent lanes (DPP wave shifts, folded into the
+//    adds); only each thread row's top and bottom cell rows go through LDS.
+//  * BX > 64: every cell is published to a copy of the region in LDS (with
+//    a zero ring) and the threads read the ring of cells around their tile.
+// A lane at the end of a thread row gets its outside neighbour from the next
+// thread row, or zero: such cells lie on the region's edge, whose values are
+// not exact anyway.
 // After s steps the cells at distance >= s from the region's edge are exact;
 // after the launch's steps (<= TT) the inner tile is stored. The grid edge is
 // handled by coordinates, never by reading outside the grid.
@@ -50,6 +57,20 @@
 #define LDS_PITCH ((RW + 2) | 1)
 #define LDS_CELLS ((RH + 2) * LDS_PITCH)
 #define LIDX(R, C) (((R) + 1) * LDS_PITCH + (C) + 1)
+// Row exchange (BX <= 64): for thread row ly, its top cell row at
+// XIDX(2 * ly + 2, C) and its bottom row at XIDX(2 * ly + 3, C); rows 1
+// (above thread row 0) and 2 * BY + 2 (below the last) stay zero.
+#define HS_ROWX (HS_BX <= 64)
+#define XROWS (2 * HS_BY + 4)
+#define XIDX(Q, C) ((Q) * RW + (C))
+#if HS_ROWX
+#define HS_LDS_FLOATS (XROWS * RW)
+#if 64 % HS_BX != 0
+#error "block_x must divide the wave size"
+#endif
+#else
+#define HS_LDS_FLOATS LDS_CELLS
+#endif
 
 #if OH < 1 || OW < 1
 #error "the region must be larger than twice the temporal tiling factor"
@@ -64,6 +85,17 @@ static __device__ __forceinline__ int xcd_remap(int id, int n_tiles)
     const int q = n_tiles >> 3, rem = n_tiles & 7;
     const int xcd = id & 7, k = id >> 3;
     return xcd * q + (xcd < rem ? xcd : rem) + k;
+}
+
+// The value of x in the lane below (lane i - 1; lane 0 gets 0) and above
+// (lane i + 1; lane 63 gets 0): DPP wave shifts.
+static __device__ __forceinline__ float lane_below(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, true));
+}
+static __device__ __forceinline__ float lane_above(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, true));
 }
 
 static __device__ __forceinline__ float cell_step(float t, float north, float south, float west, float east, float p,
@@ -83,10 +115,11 @@ static __device__ __forceinline__ float cell_step(float t, float north, float so
 // grid-edge rule, and the per-cell coordinate tests disappear.
 template <bool EDGE>
 static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const float (&pw)[HS_TY][HS_TX],
-                                                 float (*buf)[LDS_CELLS], const float* __restrict__ power,
+                                                 float (*buf)[HS_LDS_FLOATS], const float* __restrict__ power,
                                                  int rows, int cols, int steps, int R0, int C0, int gr0, int gc0,
                                                  float cc, float gx, float gy, float gz, float t_amb)
 {
+    const int ly = R0 / HS_TY;
 #if HS_UNROLL_T
 #pragma unroll 1
 #else
@@ -96,25 +129,52 @@ static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const
         if (s >= steps)
             break;
         float* cur = buf[s & 1];
+#if HS_ROWX
+#pragma unroll
+        for (int b = 0; b < HS_TX; ++b) {
+            cur[XIDX(2 * ly + 2, C0 + b)] = v[0][b];
+            cur[XIDX(2 * ly + 3, C0 + b)] = v[HS_TY - 1][b];
+        }
+#else
 #pragma unroll
         for (int a = 0; a < HS_TY; ++a)
 #pragma unroll
             for (int b = 0; b < HS_TX; ++b)
                 cur[LIDX(R0 + a, C0 + b)] = v[a][b];
+#endif
         __syncthreads();
 
         float nv[HS_TY][HS_TX];
 #pragma unroll
         for (int a = 0; a < HS_TY; ++a) {
             const int R = R0 + a, gr = gr0 + a;
+#if HS_ROWX
+            // every lane takes part in the shifts, whatever its cells need
+            const float from_west = lane_below(v[a][HS_TX - 1]);
+            const float from_east = lane_above(v[a][0]);
+#endif
 #pragma unroll
             for (int b = 0; b < HS_TX; ++b) {
                 const int C = C0 + b, gc = gc0 + b;
                 const float t = v[a][b];
                 // Neighbours: the cell itself at the grid's edge; a register
-                // inside the thread's block; else LDS (at the region's own
-                // edge, the zero ring: such cells are never exact anyway).
+                // inside the thread's block; else another thread's cell (at
+                // the region's own edge, zero: such cells are never exact).
                 float north, south, west, east;
+#if HS_ROWX
+                (void)R;
+                (void)C;
+                north = a > 0 ? v[a - 1][b] : cur[XIDX(2 * ly + 1, C0 + b)];
+                south = a < HS_TY - 1 ? v[a + 1][b] : cur[XIDX(2 * ly + 4, C0 + b)];
+                west = b > 0 ? v[a][b - 1] : from_west;
+                east = b < HS_TX - 1 ? v[a][b + 1] : from_east;
+                if (EDGE) {
+                    north = gr == 0 ? t : north;
+                    south = gr == rows - 1 ? t : south;
+                    west = gc == 0 ? t : west;
+                    east = gc == cols - 1 ? t : east;
+                }
+#else
                 if (EDGE && gr == 0) north = t;
                 else if (a > 0) north = v[a - 1][b];
                 else north = cur[LIDX(R - 1, C)];
@@ -127,6 +187,7 @@ static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const
                 if (EDGE && gc == cols - 1) east = t;
                 else if (b < HS_TX - 1) east = v[a][b + 1];
                 else east = cur[LIDX(R, C + 1)];
+#endif
 #if HS_SH_POWER
                 const float p = pw[a][b];
 #else
@@ -147,7 +208,7 @@ extern "C" __global__ void __launch_bounds__(HS_NT)
 HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* __restrict__ tout, int rows,
         int cols, int steps, int tiles_x, int n_tiles, float cc, float gx, float gy, float gz, float t_amb)
 {
-    __shared__ float buf[2][LDS_CELLS];
+    __shared__ __attribute__((aligned(16))) float buf[2][HS_LDS_FLOATS];
     const int tile = xcd_remap((int)blockIdx.x, n_tiles);
     const int tile_y = tile / tiles_x;
     const int tile_x = tile - tile_y * tiles_x;
@@ -157,23 +218,50 @@ HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* _
     const int rr0 = tile_y * OH - HS_TT, rc0 = tile_x * OW - HS_TT;   // the region's first global cell
     const int gr0 = rr0 + R0, gc0 = rc0 + C0;              // the thread's first global cell
 
-    // The thread's cells (clamped reads outside the grid: those cells are
-    // never stored and never feed a cell inside the grid).
+    // Workgroup-uniform: does the region touch (or cross) the grid's edge?
+    const bool edge = rr0 <= 0 || rc0 <= 0 || rr0 + RH >= rows || rc0 + RW >= cols;
+    // The thread's first cell as an index into the grids (negative above or
+    // left of the grid; every cell of a region that does not touch the
+    // grid's edge has an index inside it).
+    const long long base = (long long)gr0 * (long long)cols + (long long)gc0;
+
+    // The thread's cells. At the grid's edge, reads are clamped into the
+    // grid: cells outside it are never stored and never feed a cell inside.
     float v[HS_TY][HS_TX];
     float pw[HS_TY][HS_TX];
+    if (edge) {
 #pragma unroll
-    for (int a = 0; a < HS_TY; ++a) {
-        const size_t row = (size_t)clampi(gr0 + a, 0, rows - 1) * (size_t)cols;
+        for (int a = 0; a < HS_TY; ++a) {
+            const size_t row = (size_t)clampi(gr0 + a, 0, rows - 1) * (size_t)cols;
 #pragma unroll
-        for (int b = 0; b < HS_TX; ++b) {
-            const int c = clampi(gc0 + b, 0, cols - 1);
-            v[a][b] = tin[row + c];
-            pw[a][b] = HS_SH_POWER ? power[row + c] : 0.0f;
+            for (int b = 0; b < HS_TX; ++b) {
+                const int c = clampi(gc0 + b, 0, cols - 1);
+                v[a][b] = tin[row + c];
+                pw[a][b] = HS_SH_POWER ? power[row + c] : 0.0f;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < HS_TY; ++a) {
+            const long long row = base + (long long)a * (long long)cols;   // wave-uniform step per row
+#pragma unroll
+            for (int b = 0; b < HS_TX; ++b) {
+                v[a][b] = tin[row + b];
+                pw[a][b] = HS_SH_POWER ? power[row + b] : 0.0f;
+            }
         }
     }
 
-    // Zero the rings of both buffers (no thread's cells live there). The
-    // first step's barrier orders these writes before any read.
+    // Zero what no thread writes (the rows around the thread rows, or the
+    // region's ring) in both buffers. The first step's barrier orders these
+    // writes before any read.
+#if HS_ROWX
+    for (int k = (int)threadIdx.x; k < 2 * RW; k += HS_NT) {
+        const int q = k < RW ? 1 : 2 * HS_BY + 2, c = k < RW ? k : k - RW;
+        buf[0][XIDX(q, c)] = 0.0f;
+        buf[1][XIDX(q, c)] = 0.0f;
+    }
+#else
     for (int k = (int)threadIdx.x; k < 2 * (RW + 2) + 2 * RH; k += HS_NT) {
         int r, c;
         if (k < RW + 2) { r = -1; c = k - 1; }
@@ -182,25 +270,26 @@ HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* _
         buf[0][LIDX(r, c)] = 0.0f;
         buf[1][LIDX(r, c)] = 0.0f;
     }
+#endif
 
-    // Workgroup-uniform: does the region touch (or cross) the grid's edge?
-    const bool edge = rr0 <= 0 || rc0 <= 0 || rr0 + RH >= rows || rc0 + RW >= cols;
     if (edge)
         run_steps<true>(v, pw, buf, power, rows, cols, steps, R0, C0, gr0, gc0, cc, gx, gy, gz, t_amb);
     else
         run_steps<false>(v, pw, buf, power, rows, cols, steps, R0, C0, gr0, gc0, cc, gx, gy, gz, t_amb);
 
-    // Store the inner tile.
+    // Store the inner tile (cells at least TT from the region's edge; at the
+    // grid's edge, those inside the grid).
 #pragma unroll
     for (int a = 0; a < HS_TY; ++a) {
         const int R = R0 + a, gr = gr0 + a;
-        if (R < HS_TT || R >= RH - HS_TT || gr >= rows)
+        if (R < HS_TT || R >= RH - HS_TT || (edge && gr >= rows))
             continue;
+        const long long row = base + (long long)a * (long long)cols;
 #pragma unroll
         for (int b = 0; b < HS_TX; ++b) {
             const int C = C0 + b, gc = gc0 + b;
-            if (C >= HS_TT && C < RW - HS_TT && gc < cols)
-                tout[(size_t)gr * (size_t)cols + gc] = v[a][b];
+            if (C >= HS_TT && C < RW - HS_TT && (!edge || gc < cols))
+                tout[row + b] = v[a][b];
         }
     }
 }

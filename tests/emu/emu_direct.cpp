@@ -12,6 +12,7 @@ thread_local emu_dim3 blockIdx;
 emu_dim3 blockDim;
 emu_dim3 gridDim;
 std::barrier<>* emu_block_barrier;
+int* emu_dpp_slots;
 
 #include "../../paper_2407_11488_amd/csrc/conv2d_direct.hip"
 

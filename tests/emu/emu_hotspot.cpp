@@ -14,6 +14,7 @@ thread_local emu_dim3 blockIdx;
 emu_dim3 blockDim;
 emu_dim3 gridDim;
 std::barrier<>* emu_block_barrier;
+int* emu_dpp_slots;
 
 #include "../../paper_2407_11488_amd/csrc/hotspot.hip"
 
@@ -48,6 +49,8 @@ int main(int argc, char** argv)
         for (int g = 0; g < n_tiles; ++g) {
             std::barrier<> bar(HS_NT);
             emu_block_barrier = &bar;
+            std::vector<int> dpp(HS_NT);
+            emu_dpp_slots = dpp.data();
             std::vector<std::thread> th;
             for (int t = 0; t < HS_NT; ++t)
                 th.emplace_back([&, t, g] {

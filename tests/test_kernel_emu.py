@@ -159,9 +159,12 @@ def test_emulated_batch_kernel_exact(fh, fw, tmp_path):
 
 # Hotspot configurations (block_x, block_y, tile_x, tile_y, temporal,
 # unroll_t, sh_power): one cell per thread, x and y tiling, temporal factors
-# from 1 to 8 with full and partial last launches, both power modes.
+# from 1 to 8 with full and partial last launches, both power modes, thread
+# rows of 16, 32 and 64 lanes (the lane-shift exchange) and of 128 (the
+# region copy in LDS).
 HOTSPOT_CONFIGS = [(16, 4, 1, 1, 1, 1, 1), (32, 2, 2, 4, 2, 0, 0), (16, 8, 4, 2, 3, 1, 1), (64, 1, 1, 4, 1, 0, 1),
-                   (16, 16, 1, 1, 6, 0, 0), (32, 4, 2, 4, 3, 1, 0), (16, 8, 4, 4, 8, 0, 1)]
+                   (16, 16, 1, 1, 6, 0, 0), (32, 4, 2, 4, 3, 1, 0), (16, 8, 4, 4, 8, 0, 1), (64, 4, 2, 4, 6, 1, 1),
+                   (64, 2, 2, 4, 3, 0, 1), (128, 2, 2, 4, 3, 1, 1)]
 
 
 def build_hotspot(cfg):
