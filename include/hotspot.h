@@ -19,11 +19,19 @@
  * Conventions are those of conv2d.h: 0 or a negative conv2d_status, a
  * thread-local conv2d_last_error(), caller-owned dense row-major FP32 device
  * buffers checked against their allocations, asynchronous work on `stream`.
- * Every cell is evaluated by the same FP32 expression in the same order
- * (t2 = T + T; ly = (N + S) - t2; lx = (W + E) - t2; f = fma(ly, gy, P);
- * f = fma(lx, gx, f); f = fma(t_amb - T, gz, f); T' = fma(f, cc, T)), so
- * results are bitwise identical across configurations and
- * hotspot_reference.
+ * Every cell is evaluated by the same FP32 expression in the same order,
+ * the step's terms regrouped by what they multiply:
+ *
+ *     T' = a*T + ky*(N + S) + kx*(W + E) + (cc*P + q),
+ *     a = 1 - cc*(2gx + 2gy + gz), ky = cc*gy, kx = cc*gx, q = cc*gz*t_amb,
+ *
+ * the four coefficients computed once per call in double from the given
+ * FP32 ones and rounded to FP32, then s = fma(cc, P, q), x = fma(kx, W + E,
+ * s), x = fma(ky, N + S, x), T' = fma(a, T, x).
+ * Results are bitwise identical across configurations and
+ * hotspot_reference, and within 8 n 2^-24 (max|T| + |t_amb| + n cc max|P|)
+ * of the exact n steps while a >= 0 (coefficients inside the explicit step's
+ * stability limit).
  */
 #ifndef HOTSPOT_H
 #define HOTSPOT_H

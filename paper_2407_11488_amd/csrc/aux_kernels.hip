@@ -97,11 +97,12 @@ __global__ void flush_kernel(const float4* __restrict__ d, size_t n4, float* __r
 }
 
 // One explicit hotspot step, one cell per thread (the hotspot tuner's
-// reference). The cell's expression and its order are those of the tunable
-// hotspot kernel; a neighbour outside the grid is the cell itself.
+// reference). The cell's expression, its grouping of terms and its order are
+// those of the tunable hotspot kernel; a neighbour outside the grid is the
+// cell itself.
 __global__ void __launch_bounds__(256)
 hotspot_reference_kernel(const float* __restrict__ tin, const float* __restrict__ power, float* __restrict__ tout,
-                         int rows, int cols, float cc, float gx, float gy, float gz, float t_amb)
+                         int rows, int cols, float ka, float ky, float kx, float cc, float q)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)rows * cols) return;
@@ -112,13 +113,9 @@ hotspot_reference_kernel(const float* __restrict__ tin, const float* __restrict_
     const float south = r < rows - 1 ? tin[idx + cols] : t;
     const float west = c > 0 ? tin[idx - 1] : t;
     const float east = c < cols - 1 ? tin[idx + 1] : t;
-    const float t2 = t + t;
-    const float lap_y = (north + south) - t2;
-    const float lap_x = (west + east) - t2;
-    float flow = __builtin_fmaf(lap_y, gy, power[idx]);
-    flow = __builtin_fmaf(lap_x, gx, flow);
-    flow = __builtin_fmaf(t_amb - t, gz, flow);
-    tout[idx] = __builtin_fmaf(flow, cc, t);
+    float x = __builtin_fmaf(kx, west + east, __builtin_fmaf(cc, power[idx], q));
+    x = __builtin_fmaf(ky, north + south, x);
+    tout[idx] = __builtin_fmaf(ka, t, x);
 }
 
 int grid_for(size_t n, int block)
@@ -143,13 +140,13 @@ int launch_reference(const conv2d_shape& s, const float* d_in, const float* d_f,
 }
 
 int launch_hotspot_reference_step(int rows, int cols, const float* d_in, const float* d_power, float* d_out,
-                                  float cc, float gx, float gy, float gz, float t_amb, hipStream_t stream)
+                                  const hs_terms& k, hipStream_t stream)
 {
     const long long n = (long long)rows * cols;
     const long long blocks = (n + 255) / 256;
     if (blocks > 0x7fffffffll) return fail(CONV2D_EINVAL, "hotspot reference: grid too large");
     hipLaunchKernelGGL(hotspot_reference_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, d_in, d_power, d_out,
-                       rows, cols, cc, gx, gy, gz, t_amb);
+                       rows, cols, k.ka, k.ky, k.kx, k.cc, k.q);
     CONV2D_HIP(hipGetLastError());
     return CONV2D_OK;
 }

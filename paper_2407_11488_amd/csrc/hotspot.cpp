@@ -132,11 +132,11 @@ int hs_launch(const Module& m, const hotspot_config& c, const hotspot_shape& s, 
     const HsGeometry g = hs_geometry(s, c);
     if (g.n_tiles < 1) return fail(CONV2D_EINVAL, "hotspot: too many tiles for one launch");
     int rows = s.rows, cols = s.cols, tiles_x = g.tiles_x, n_tiles = g.n_tiles;
-    float cc = k.cc, gx = k.gx, gy = k.gy, gz = k.gz, ta = k.t_amb;
+    hs_terms t = hs_fold(k);
     const void* a_in = tin;
     const void* a_pw = power;
     void* a_out = tout;
-    void* args[] = {&a_in, &a_pw, &a_out, &rows, &cols, &steps, &tiles_x, &n_tiles, &cc, &gx, &gy, &gz, &ta};
+    void* args[] = {&a_in, &a_pw, &a_out, &rows, &cols, &steps, &tiles_x, &n_tiles, &t.ka, &t.ky, &t.kx, &t.cc, &t.q};
     hipError_t e = hipModuleLaunchKernel(m.fn, (unsigned)n_tiles, 1, 1, (unsigned)(c.block_x * c.block_y), 1, 1, 0,
                                          st, args, nullptr);
     if (e != hipSuccess) return fail(CONV2D_ELAUNCH, std::string("hotspot launch: ") + hipGetErrorString(e));
@@ -338,8 +338,7 @@ public:
         if (rc) return rc;
         k_ = hotspot_coeffs{0.2f, 0.5f, 0.75f, 0.05f, 0.25f};
         rc = ping_pong(steps_, d_temp_, d_ref_, d_work_, [&](int, const float* src, float* dst) {
-            return launch_hotspot_reference_step(s_.rows, s_.cols, src, d_power_, dst, k_.cc, k_.gx, k_.gy, k_.gz,
-                                                 k_.t_amb, stream_);
+            return launch_hotspot_reference_step(s_.rows, s_.cols, src, d_power_, dst, hs_fold(k_), stream_);
         });
         if (rc) return rc;
         // Copies of (temperature, power, output, work) for sustained timing:
@@ -520,6 +519,13 @@ void load_hs_results(const std::string& path, const std::string& arch, const hot
 }  // namespace
 
 const std::string& hotspot_source() { return hs_source(); }
+
+hs_terms hs_fold(const hotspot_coeffs& k)
+{
+    const double cc = k.cc, gx = k.gx, gy = k.gy, gz = k.gz, ta = k.t_amb;
+    return hs_terms{(float)(1.0 - cc * (2.0 * gx + 2.0 * gy + gz)), (float)(cc * gy), (float)(cc * gx), k.cc,
+                    (float)(cc * gz * ta)};
+}
 
 }  // namespace conv2d
 
@@ -726,8 +732,9 @@ extern "C" int hotspot_reference(hotspot_shape s, const float* d_temp, const flo
         CONV2D_HIP(hipMemcpyAsync(d_out, d_temp, 4ull * (size_t)s.rows * (size_t)s.cols, hipMemcpyDeviceToDevice, st));
         return CONV2D_OK;
     }
+    const hs_terms t = hs_fold(k);
     return ping_pong(steps, d_temp, d_out, d_work, [&](int, const float* src, float* dst) {
-        return launch_hotspot_reference_step(s.rows, s.cols, src, d_power, dst, k.cc, k.gx, k.gy, k.gz, k.t_amb, st);
+        return launch_hotspot_reference_step(s.rows, s.cols, src, d_power, dst, t, st);
     });
 }
 

@@ -7,10 +7,14 @@
 //   T'[r][c] = T + cc * (P + (T[r-1][c] + T[r+1][c] - 2T) * gy
 //                          + (T[r][c-1] + T[r][c+1] - 2T) * gx
 //                          + (t_amb - T) * gz)
-// where a neighbour outside the grid is the cell itself. Every cell is
-// evaluated by the same FP32 expression in the same order (two sums of
-// neighbours, then four fused multiply-adds), so every configuration returns
-// the same bits.
+// where a neighbour outside the grid is the cell itself. The kernel evaluates
+// the same step with its terms grouped by what they multiply,
+//   T' = a*T + ky*(N + S) + kx*(W + E) + s,   s = cc*P + q,
+// a = 1 - cc*(2gx + 2gy + gz), ky = cc*gy, kx = cc*gx, q = cc*gz*t_amb
+// (folded by the host): two neighbour sums and three fused multiply-adds per
+// cell and step, s once per cell and launch when power stays on chip. Every
+// cell is evaluated in the same order, so every configuration returns the
+// same bits.
 //
 // Compile-time parameters (-D):
 //   HS_BX, HS_BY   workgroup shape in threads (block_size_x / block_size_y)
@@ -36,7 +40,10 @@
 // not exact anyway.
 // After s steps the cells at distance >= s from the region's edge are exact;
 // after the launch's steps (<= TT) the inner tile is stored. The grid edge is
-// handled by coordinates, never by reading outside the grid.
+// handled by coordinates, never by reading outside the grid. A region inside
+// the grid reads and writes through raw buffers based at its first cell
+// (32-bit offsets: one address per thread, rows by a scalar offset), with
+// every load issued before the first one is waited for.
 
 #ifndef HS_BX
 #error "HS_BX must be defined"
@@ -78,6 +85,13 @@
 
 static __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// A raw buffer over `bytes` bytes from p (dword access; word 3 is the gfx9
+// family's raw-buffer value).
+static __device__ __forceinline__ __amdgpu_buffer_rsrc_t region_rsrc(const float* p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+
 // Workgroup id -> tile id: XCD x (= id mod 8) gets one contiguous run of
 // tiles, so neighbouring tiles, which share halo cells, meet in one L2.
 static __device__ __forceinline__ int xcd_remap(int id, int n_tiles)
@@ -98,16 +112,15 @@ static __device__ __forceinline__ float lane_above(float x)
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, true));
 }
 
-static __device__ __forceinline__ float cell_step(float t, float north, float south, float west, float east, float p,
-                                                  float cc, float gx, float gy, float gz, float t_amb)
+// A cell's source term: its power and the ambient's share, per step.
+static __device__ __forceinline__ float source(float p, float cc, float q) { return __builtin_fmaf(cc, p, q); }
+
+static __device__ __forceinline__ float cell_step(float t, float north, float south, float west, float east, float src,
+                                                  float ka, float ky, float kx)
 {
-    const float t2 = t + t;
-    const float lap_y = (north + south) - t2;
-    const float lap_x = (west + east) - t2;
-    float flow = __builtin_fmaf(lap_y, gy, p);
-    flow = __builtin_fmaf(lap_x, gx, flow);
-    flow = __builtin_fmaf(t_amb - t, gz, flow);
-    return __builtin_fmaf(flow, cc, t);
+    float x = __builtin_fmaf(kx, west + east, src);
+    x = __builtin_fmaf(ky, north + south, x);
+    return __builtin_fmaf(ka, t, x);
 }
 
 // The launch's steps over the thread's cells v (in place). EDGE = false when
@@ -117,7 +130,7 @@ template <bool EDGE>
 static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const float (&pw)[HS_TY][HS_TX],
                                                  float (*buf)[HS_LDS_FLOATS], const float* __restrict__ power,
                                                  int rows, int cols, int steps, int R0, int C0, int gr0, int gc0,
-                                                 float cc, float gx, float gy, float gz, float t_amb)
+                                                 float ka, float ky, float kx, float cc, float q)
 {
     const int ly = R0 / HS_TY;
 #if HS_UNROLL_T
@@ -189,11 +202,14 @@ static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const
                 else east = cur[LIDX(R, C + 1)];
 #endif
 #if HS_SH_POWER
-                const float p = pw[a][b];
+                const float src = pw[a][b];
+                (void)cc;
+                (void)q;
 #else
-                const float p = power[(size_t)clampi(gr, 0, rows - 1) * (size_t)cols + clampi(gc, 0, cols - 1)];
+                const float src =
+                    source(power[(size_t)clampi(gr, 0, rows - 1) * (size_t)cols + clampi(gc, 0, cols - 1)], cc, q);
 #endif
-                nv[a][b] = cell_step(t, north, south, west, east, p, cc, gx, gy, gz, t_amb);
+                nv[a][b] = cell_step(t, north, south, west, east, src, ka, ky, kx);
             }
         }
 #pragma unroll
@@ -206,7 +222,7 @@ static __device__ __forceinline__ void run_steps(float (&v)[HS_TY][HS_TX], const
 
 extern "C" __global__ void __launch_bounds__(HS_NT)
 HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* __restrict__ tout, int rows,
-        int cols, int steps, int tiles_x, int n_tiles, float cc, float gx, float gy, float gz, float t_amb)
+        int cols, int steps, int tiles_x, int n_tiles, float ka, float ky, float kx, float cc, float q)
 {
     __shared__ __attribute__((aligned(16))) float buf[2][HS_LDS_FLOATS];
     const int tile = xcd_remap((int)blockIdx.x, n_tiles);
@@ -219,14 +235,18 @@ HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* _
     const int gr0 = rr0 + R0, gc0 = rc0 + C0;              // the thread's first global cell
 
     // Workgroup-uniform: does the region touch (or cross) the grid's edge?
-    const bool edge = rr0 <= 0 || rc0 <= 0 || rr0 + RH >= rows || rc0 + RW >= cols;
-    // The thread's first cell as an index into the grids (negative above or
-    // left of the grid; every cell of a region that does not touch the
-    // grid's edge has an index inside it).
-    const long long base = (long long)gr0 * (long long)cols + (long long)gc0;
+    // (Regions whose rows span 2^31 bytes or more take the same clamped path.)
+    const bool edge = rr0 <= 0 || rc0 <= 0 || rr0 + RH >= rows || rc0 + RW >= cols ||
+                      (long long)RH * (long long)cols >= (1ll << 29);
+    // Inside the grid, the region's rows are one buffer starting at its first
+    // cell; a thread's cell (a, b) sits at byte voff + 4 * (a * cols + b).
+    const long long rbase = (long long)rr0 * (long long)cols + (long long)rc0;
+    const unsigned rbytes = (unsigned)(RH * cols) * 4u;
+    const unsigned voff = (unsigned)(R0 * cols + C0) * 4u;
 
-    // The thread's cells. At the grid's edge, reads are clamped into the
-    // grid: cells outside it are never stored and never feed a cell inside.
+    // The thread's cells (and with power on chip, their source terms). At
+    // the grid's edge, reads are clamped into the grid: cells outside it are
+    // never stored and never feed a cell inside.
     float v[HS_TY][HS_TX];
     float pw[HS_TY][HS_TX];
     if (edge) {
@@ -237,19 +257,30 @@ HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* _
             for (int b = 0; b < HS_TX; ++b) {
                 const int c = clampi(gc0 + b, 0, cols - 1);
                 v[a][b] = tin[row + c];
-                pw[a][b] = HS_SH_POWER ? power[row + c] : 0.0f;
+                pw[a][b] = HS_SH_POWER ? source(power[row + c], cc, q) : 0.0f;
             }
         }
     } else {
+        const __amdgpu_buffer_rsrc_t rt = region_rsrc(tin + rbase, rbytes);
+        const __amdgpu_buffer_rsrc_t rp = region_rsrc(power + rbase, rbytes);
+        float praw[HS_TY][HS_TX];
 #pragma unroll
-        for (int a = 0; a < HS_TY; ++a) {
-            const long long row = base + (long long)a * (long long)cols;   // wave-uniform step per row
+        for (int a = 0; a < HS_TY; ++a)
 #pragma unroll
             for (int b = 0; b < HS_TX; ++b) {
-                v[a][b] = tin[row + b];
-                pw[a][b] = HS_SH_POWER ? power[row + b] : 0.0f;
+                const int so = a * cols * 4;   // wave-uniform
+                v[a][b] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rt, (int)(voff + 4u * b), so, 0));
+                praw[a][b] = HS_SH_POWER
+                    ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, (int)(voff + 4u * b), so, 0))
+                    : 0.0f;
             }
-        }
+        // every load is in flight before the first source term waits for one
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < HS_TY; ++a)
+#pragma unroll
+            for (int b = 0; b < HS_TX; ++b)
+                pw[a][b] = HS_SH_POWER ? source(praw[a][b], cc, q) : 0.0f;
     }
 
     // Zero what no thread writes (the rows around the thread rows, or the
@@ -273,23 +304,41 @@ HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* _
 #endif
 
     if (edge)
-        run_steps<true>(v, pw, buf, power, rows, cols, steps, R0, C0, gr0, gc0, cc, gx, gy, gz, t_amb);
+        run_steps<true>(v, pw, buf, power, rows, cols, steps, R0, C0, gr0, gc0, ka, ky, kx, cc, q);
     else
-        run_steps<false>(v, pw, buf, power, rows, cols, steps, R0, C0, gr0, gc0, cc, gx, gy, gz, t_amb);
+        run_steps<false>(v, pw, buf, power, rows, cols, steps, R0, C0, gr0, gc0, ka, ky, kx, cc, q);
 
     // Store the inner tile (cells at least TT from the region's edge; at the
     // grid's edge, those inside the grid).
+    if (edge) {
+        const long long base = (long long)gr0 * (long long)cols + (long long)gc0;
 #pragma unroll
-    for (int a = 0; a < HS_TY; ++a) {
-        const int R = R0 + a, gr = gr0 + a;
-        if (R < HS_TT || R >= RH - HS_TT || (edge && gr >= rows))
-            continue;
-        const long long row = base + (long long)a * (long long)cols;
+        for (int a = 0; a < HS_TY; ++a) {
+            const int R = R0 + a, gr = gr0 + a;
+            if (R < HS_TT || R >= RH - HS_TT || gr >= rows)
+                continue;
+            const long long row = base + (long long)a * (long long)cols;
 #pragma unroll
-        for (int b = 0; b < HS_TX; ++b) {
-            const int C = C0 + b, gc = gc0 + b;
-            if (C >= HS_TT && C < RW - HS_TT && (!edge || gc < cols))
-                tout[row + b] = v[a][b];
+            for (int b = 0; b < HS_TX; ++b) {
+                const int C = C0 + b, gc = gc0 + b;
+                if (C >= HS_TT && C < RW - HS_TT && gc < cols)
+                    tout[row + b] = v[a][b];
+            }
+        }
+    } else {
+        const __amdgpu_buffer_rsrc_t ro = region_rsrc(tout + rbase, rbytes);
+#pragma unroll
+        for (int a = 0; a < HS_TY; ++a) {
+            const int R = R0 + a;
+            if (R < HS_TT || R >= RH - HS_TT)
+                continue;
+#pragma unroll
+            for (int b = 0; b < HS_TX; ++b) {
+                const int C = C0 + b;
+                if (C >= HS_TT && C < RW - HS_TT)
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v[a][b]), ro,
+                                                          (int)(voff + 4u * b), a * cols * 4, 0);
+            }
         }
     }
 }

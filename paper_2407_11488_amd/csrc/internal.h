@@ -123,9 +123,17 @@ int launch_direct(const Module& m, const conv2d_shape& s, const conv2d_config& c
 // ---------------------------------------------------------------- aux kernels
 int launch_reference(const conv2d_shape& s, const float* d_in, const float* d_f, float* d_out,
                      hipStream_t stream);
+// The hotspot step's coefficients grouped by the term they multiply
+// (T' = ka*T + ky*(N + S) + kx*(W + E) + fma(cc, P, q)), computed in double
+// from the caller's FP32 coefficients and rounded once; the tunable kernel
+// and the reference take the same values.
+struct hs_terms {
+    float ka, ky, kx, cc, q;
+};
+hs_terms hs_fold(const hotspot_coeffs& k);
 // One explicit hotspot step, one cell per thread (see hotspot.h).
 int launch_hotspot_reference_step(int rows, int cols, const float* d_in, const float* d_power, float* d_out,
-                                  float cc, float gx, float gy, float gz, float t_amb, hipStream_t stream);
+                                  const hs_terms& k, hipStream_t stream);
 int launch_fill_uniform(float* d, size_t n, uint64_t seed, uint64_t start, hipStream_t stream);
 int launch_fill_value(float* d, size_t n, float v, hipStream_t stream);
 // Counts words of a and b whose bits differ; *d_count must be a device int.

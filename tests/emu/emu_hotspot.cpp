@@ -34,6 +34,11 @@ int main(int argc, char** argv)
     const float cc = std::strtof(argv[4], nullptr), gx = std::strtof(argv[5], nullptr);
     const float gy = std::strtof(argv[6], nullptr), gz = std::strtof(argv[7], nullptr);
     const float ta = std::strtof(argv[8], nullptr);
+    // The step's coefficients grouped by term, as the library's host code
+    // passes them: computed in double, rounded once.
+    const float ka = (float)(1.0 - (double)cc * (2.0 * gx + 2.0 * gy + gz));
+    const float ky = (float)((double)cc * gy), kx = (float)((double)cc * gx);
+    const float q = (float)((double)cc * gz * ta);
     const std::string dir = argv[9];
     const size_t n = (size_t)rows * cols;
     std::vector<float> temp = read_all(dir + "/temp.f32", n), power = read_all(dir + "/power.f32", n);
@@ -56,7 +61,7 @@ int main(int argc, char** argv)
                 th.emplace_back([&, t, g] {
                     threadIdx = {(unsigned)t, 0, 0};
                     blockIdx = {(unsigned)g, 0, 0};
-                    HS_NAME(src, power.data(), dst, rows, cols, this_steps, tiles_x, n_tiles, cc, gx, gy, gz, ta);
+                    HS_NAME(src, power.data(), dst, rows, cols, this_steps, tiles_x, n_tiles, ka, ky, kx, cc, q);
                 });
             for (auto& x : th) x.join();
         }

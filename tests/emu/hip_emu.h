@@ -82,13 +82,27 @@ inline void emu_buffer_read(__amdgpu_buffer_rsrc_t r, int off, int n, uint32_t* 
 typedef unsigned int emu_u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int emu_u32x4 __attribute__((ext_vector_type(4)));
 
+// The scalar offset adds to the byte offset; the range check here takes the
+// sum (stricter than a check of the vector offset alone), so an access the
+// kernel relies on must be in range either way.
 inline unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
 {
-    assert(soff == 0 && aux == 0);
+    assert(soff >= 0 && aux == 0);
     uint32_t v;
-    emu_buffer_read(r, off, 1, &v);
+    emu_buffer_read(r, (int)((uint32_t)off + (uint32_t)soff), 1, &v);
     return v;
 }
+
+// A store outside num_records is dropped.
+inline void __builtin_amdgcn_raw_buffer_store_b32(unsigned v, __amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
+{
+    assert(soff >= 0 && aux == 0);
+    const uint64_t o = (uint64_t)(uint32_t)off + (uint64_t)(uint32_t)soff;
+    if (o + 4 <= r.num_records)
+        std::memcpy(const_cast<char*>(r.base) + o, &v, 4);  // ASan checks the allocation
+}
+
+inline void __builtin_amdgcn_sched_barrier(int) {}
 
 inline emu_u32x2 __builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
 {

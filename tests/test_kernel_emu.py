@@ -184,16 +184,15 @@ def build_hotspot(cfg):
     return exe
 
 
-def test_emulated_hotspot_kernel(tmp_path):
-    """The temporally tiled hotspot kernel on uneven grids (smaller than one
-    tile, several tiles with ragged edges, one row, one column): every
-    configuration returns the same bits, within the FP32 bound of the FP64
+def _check_hotspot(tmp_path, cfgs, grids):
+    """Every configuration in cfgs on every (rows, cols, steps) grid: the
+    same bits across configurations, within the FP32 bound of the FP64
     oracle."""
     with cf.ThreadPoolExecutor(os.cpu_count() or 4) as ex:
-        exes = list(ex.map(build_hotspot, HOTSPOT_CONFIGS))
+        exes = list(ex.map(build_hotspot, cfgs))
     k = (0.2, 0.5, 0.75, 0.05, 0.25)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    for (rows, cols, steps) in [(37, 45, 7), (5, 130, 3), (1, 9, 4), (23, 1, 5), (70, 3, 9), (2, 2, 0)]:
+    for (rows, cols, steps) in grids:
         temp = datagen.uniform_pm1(61, rows * cols).reshape(rows, cols)
         power = datagen.uniform_pm1(62, rows * cols).reshape(rows, cols)
         temp.tofile(tmp_path / "temp.f32")
@@ -201,7 +200,7 @@ def test_emulated_hotspot_kernel(tmp_path):
         ref = oracle.hotspot_f64(temp, power, steps, *k)
         bound = 8 * max(steps, 1) * 2.0 ** -24 * (1.0 + abs(k[4]) + steps * k[0] * 1.0)
         first = None
-        for cfg, exe in zip(HOTSPOT_CONFIGS, exes):
+        for cfg, exe in zip(cfgs, exes):
             r = subprocess.run([exe, str(rows), str(cols), str(steps), *[repr(v) for v in k], str(tmp_path)],
                                capture_output=True, text=True, env=env, timeout=300)
             assert r.returncode == 0, r.stderr[-3000:]
@@ -211,3 +210,17 @@ def test_emulated_hotspot_kernel(tmp_path):
             if first is None:
                 first = got
             assert np.array_equal(got.view(np.uint32), first.view(np.uint32)), (cfg, rows, cols)
+
+
+def test_emulated_hotspot_kernel(tmp_path):
+    """The temporally tiled hotspot kernel on uneven grids (smaller than one
+    tile, several tiles with ragged edges, one row, one column)."""
+    _check_hotspot(tmp_path, HOTSPOT_CONFIGS, [(37, 45, 7), (5, 130, 3), (1, 9, 4), (23, 1, 5), (70, 3, 9), (2, 2, 0)])
+
+
+def test_emulated_hotspot_interior_regions(tmp_path):
+    """Grids with regions away from every edge (the buffer-addressed loads and
+    stores) beside edge regions, for configurations whose regions fit inside
+    them several times: 64 x 16 and 64 x 8 cells, 128 x 8."""
+    _check_hotspot(tmp_path, [(32, 4, 2, 4, 3, 1, 1), (16, 8, 4, 2, 2, 1, 0), (64, 2, 2, 4, 3, 0, 1)],
+                   [(130, 200, 7), (61, 300, 4)])
