@@ -359,6 +359,9 @@ def tune_serving(rate_fraction: float = 0.8, duration: float = 3.0, budget_gib: 
     return res
 
 
+# The update as written (2T, two neighbour sums, two differences, t_amb - T,
+# four multiply-adds); the kernel evaluates it regrouped with 8 (two adds,
+# three multiply-adds), and "gcell_steps" states the rate without a convention.
 HOTSPOT_FLOP_PER_CELL_STEP = 14
 HOTSPOT_BYTES_PER_CELL_LAUNCH = 12   # read temperature and power, write temperature
 
@@ -387,6 +390,7 @@ def hotspot_benchmark(reps: int = 20, warmup: int = 3, steps: int = 60, rows: in
         res[name] = {
             "config": list(plan.config), "source": plan.source, "ms": round(ms, 4),
             "gflops": round(HOTSPOT_FLOP_PER_CELL_STEP * rows * cols * steps / (ms * 1e-3) / 1e9, 1),
+            "gcell_steps": round(rows * cols * steps / (ms * 1e-3) / 1e9, 1),
             "launches": launches, "ms_per_launch": round(ms / launches, 4),
             "gbs_per_launch": round(HOTSPOT_BYTES_PER_CELL_LAUNCH * rows * cols / (ms / launches * 1e-3) / 1e9, 1),
         }
