@@ -431,7 +431,7 @@ def main(argv=None) -> int:
                                      "winner applied unchanged)")
     w.add_argument("--reps", type=int, default=60)
     w.add_argument("--filters", type=int, nargs="*", default=list(SWEEP_FILTERS))
-    for sp in (w, h):
+    for sp in (w, h, b):
         sp.add_argument("--calib-copy-mib", type=int, default=0,
                         help="afterwards, negate this many MiB with torch (a plain elementwise kernel of "
                              "known traffic: calibration of the profiler's byte counters)")
