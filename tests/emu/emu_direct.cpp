@@ -13,6 +13,7 @@ emu_dim3 blockDim;
 emu_dim3 gridDim;
 std::barrier<>* emu_block_barrier;
 int* emu_dpp_slots;
+std::barrier<>** emu_wave_barriers;
 
 #include "../../paper_2407_11488_amd/csrc/conv2d_direct.hip"
 

@@ -5,6 +5,7 @@
 // and power.f32; writes out.f32)
 #include "hip_emu.h"
 
+#include <memory>
 #include <string>
 #include <thread>
 #include <vector>
@@ -15,6 +16,7 @@ emu_dim3 blockDim;
 emu_dim3 gridDim;
 std::barrier<>* emu_block_barrier;
 int* emu_dpp_slots;
+std::barrier<>** emu_wave_barriers;
 
 #include "../../paper_2407_11488_amd/csrc/hotspot.hip"
 
@@ -56,6 +58,13 @@ int main(int argc, char** argv)
             emu_block_barrier = &bar;
             std::vector<int> dpp(HS_NT);
             emu_dpp_slots = dpp.data();
+            std::vector<std::unique_ptr<std::barrier<>>> waves;
+            std::vector<std::barrier<>*> wave_ptrs;
+            for (int w0 = 0; w0 < HS_NT; w0 += 64) {
+                waves.emplace_back(new std::barrier<>(std::min(64, HS_NT - w0)));
+                wave_ptrs.push_back(waves.back().get());
+            }
+            emu_wave_barriers = wave_ptrs.data();
             std::vector<std::thread> th;
             for (int t = 0; t < HS_NT; ++t)
                 th.emplace_back([&, t, g] {

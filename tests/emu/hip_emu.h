@@ -36,22 +36,25 @@ inline void __syncthreads() { emu_block_barrier->arrive_and_wait(); }
 
 // DPP wave shifts by one lane (wave_shr:1 = 0x138: lane i reads lane i-1;
 // wave_shl:1 = 0x130: lane i reads lane i+1), 64-lane waves, lanes outside
-// the wave reading 0 (bound_ctrl) or `old`. Every thread of the block must
-// call it together (as the kernels do: the shifts sit in uniform control
-// flow): each publishes its value, waits, reads its neighbour's, waits.
-extern int* emu_dpp_slots;   // blockDim.x ints, set by the launcher
+// the wave reading 0 (bound_ctrl) or `old`. Every thread of a wave must
+// call it together (as the kernels do: the shifts sit in wave-uniform
+// control flow): each publishes its value, waits for its wave, reads its
+// neighbour's, waits again.
+extern int* emu_dpp_slots;                  // blockDim.x ints, set by the launcher
+extern std::barrier<>** emu_wave_barriers;  // one per 64-lane wave of the block, set by the launcher
 inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl)
 {
     assert(row_mask == 0xf && bank_mask == 0xf && (ctrl == 0x138 || ctrl == 0x130));
     const unsigned t = threadIdx.x, lane = t % 64, wave0 = t - lane;
+    std::barrier<>* wave = emu_wave_barriers[t / 64];
     emu_dpp_slots[t] = src;
-    emu_block_barrier->arrive_and_wait();
+    wave->arrive_and_wait();
     int r;
     if (ctrl == 0x138)
         r = lane == 0 ? (bound_ctrl ? 0 : old) : emu_dpp_slots[wave0 + lane - 1];
     else
         r = lane == 63 ? (bound_ctrl ? 0 : old) : emu_dpp_slots[wave0 + lane + 1];
-    emu_block_barrier->arrive_and_wait();
+    wave->arrive_and_wait();
     return r;
 }
 

@@ -61,9 +61,9 @@ def build(cfg, fh, fw, vin, vout):
     if not os.path.exists(exe):
         cmd = [CXX, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                "-fno-omit-frame-pointer", *[f"-DCONV_{k}={v}" for k, v in defs.items()],
-               os.path.join(EMU, "emu_direct.cpp"), "-o", exe + ".tmp", "-lpthread"]
+               os.path.join(EMU, "emu_direct.cpp"), "-o", exe + f".{os.getpid()}.tmp", "-lpthread"]
         subprocess.run(cmd, check=True, capture_output=True)
-        os.replace(exe + ".tmp", exe)
+        os.replace(exe + f".{os.getpid()}.tmp", exe)
     return exe
 
 
@@ -124,9 +124,9 @@ def build_batch(cfg, fh, fw):
     if not os.path.exists(exe):
         cmd = [CXX, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                "-fno-omit-frame-pointer", *[f"-DCONV_{k}={v}" for k, v in defs.items()],
-               os.path.join(EMU, "emu_batch.cpp"), "-o", exe + ".tmp", "-lpthread"]
+               os.path.join(EMU, "emu_batch.cpp"), "-o", exe + f".{os.getpid()}.tmp", "-lpthread"]
         subprocess.run(cmd, check=True, capture_output=True)
-        os.replace(exe + ".tmp", exe)
+        os.replace(exe + f".{os.getpid()}.tmp", exe)
     return exe
 
 
@@ -178,9 +178,9 @@ def build_hotspot(cfg):
     if not os.path.exists(exe):
         cmd = [CXX, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                "-fno-omit-frame-pointer", *[f"-DHS_{k}={v}" for k, v in defs.items()],
-               "-DHS_NAME=hotspot_emu", os.path.join(EMU, "emu_hotspot.cpp"), "-o", exe + ".tmp", "-lpthread"]
+               "-DHS_NAME=hotspot_emu", os.path.join(EMU, "emu_hotspot.cpp"), "-o", exe + f".{os.getpid()}.tmp", "-lpthread"]
         subprocess.run(cmd, check=True, capture_output=True)
-        os.replace(exe + ".tmp", exe)
+        os.replace(exe + f".{os.getpid()}.tmp", exe)
     return exe
 
 
