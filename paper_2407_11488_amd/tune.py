@@ -18,6 +18,10 @@ The served path's configurations per filter size and size bucket (sizes up
 to 384, 768, 1536, 3072 and above), tuned on a sample of shapes drawn like the
 served workload's, stored as the (0, bucket, fh, fw) winners:
     python -m paper_2407_11488_amd.tune --buckets [--sample 160]
+The batched path's configurations chosen in context (each group's
+candidates timed as the whole 64-problem batch, the other groups held,
+coordinate descent; appended as the (0, 0, fh, fw) winners):
+    python -m paper_2407_11488_amd.tune --batch-context [--candidates 24] [--rounds 2]
 The server's stream count and batch-size cap (streams 1-8 x caps 1-256, each
 serving one Poisson trace at a fraction of serial capacity; lowest p99 wins),
 stored in tuned/serve_params.json:
@@ -153,7 +157,11 @@ def main(argv=None) -> int:
     ap.add_argument("--json", default=None)
     ap.add_argument("--hotspot", type=int, nargs=2, metavar=("ROWS", "COLS"))
     ap.add_argument("--batch", action="store_true")
-    ap.add_argument("--candidates", type=int, default=12)
+    ap.add_argument("--batch-context", action="store_true",
+                    help="the batched groups' configurations by the whole batch's time (coordinate descent)")
+    ap.add_argument("--rounds", type=int, default=2, help="--batch-context: passes over the groups")
+    ap.add_argument("--candidates", type=int, default=None,
+                    help="sweep points tried per group (default 12; --batch-context: 24)")
     ap.add_argument("--buckets", action="store_true",
                     help="batched kernels per filter size and size bucket, on a sample of served shapes")
     ap.add_argument("--sample", type=int, default=160)
@@ -168,12 +176,17 @@ def main(argv=None) -> int:
         from . import workloads
         emit(workloads.tune_serving(a.rate, a.duration), a.json)
         return 0
+    if a.batch_context:
+        from . import workloads
+        emit(workloads.batch_context_tune(candidates=a.candidates or 24, rounds=a.rounds, winners=a.winners,
+                                          results_dir=a.results_dir), a.json)
+        return 0
     if a.batch or a.buckets:
         import datagen
         o = B.conv2d_batch_tune_defaults()
         o.winners_path = a.winners.encode()
         o.results_dir = (a.results_dir or os.path.dirname(DEFAULT_WINNERS)).encode()
-        o.candidates, o.verbose = a.candidates, 1
+        o.candidates, o.verbose = a.candidates or 12, 1
         if a.buckets:
             # one configuration per filter size and size bucket, tuned on a
             # sample of the served distribution

@@ -313,3 +313,36 @@ def test_batch_tune_by_size_bucket(tmp_path, monkeypatch):
         if got is not None:
             assert tuple(x["config"])[:6] == got[0].tuple()[:6]
     whole.close()
+
+
+def test_batch_context_tune_stores_and_is_used(tmp_path, monkeypatch):
+    """The in-context tuning of the batched path (workloads.batch_context_tune)
+    on the first 12 problems of the batched workload, two candidates per
+    group, one pass: every trial's outputs equal the first trial's bit for
+    bit (checked inside), the result covers every filter group, the chosen
+    configurations are appended as the (0, 0, fh, fw) winners, and a batch
+    planned afterwards uses them and matches the oracle."""
+    import shutil
+
+    from paper_2407_11488_amd import workloads
+    torch = torch_cuda()
+    wp = tmp_path / "winners.jsonl"
+    shutil.copy(os.path.join(os.path.dirname(C.LIB_PATH), "tuned", "winners.jsonl"), wp)
+    monkeypatch.delenv("CONV2D_WINNERS", raising=False)
+    r = workloads.batch_context_tune(n=12, candidates=2, rounds=1, reps=5, winners=str(wp), log=say)
+    say(f"batch context tune: {r}")
+    shapes = datagen.batch_shapes(12)
+    filters = sorted({s[2] for s in shapes})
+    assert sorted(int(f) for f in r["assignment"]) == filters
+    assert r["trials"] >= 1 and r["final_ms"] > 0 and r["best_ms"] <= r["start_ms"]
+    assert os.environ.get("CONV2D_WINNERS") is None          # restored
+    for f, cfg in r["assignment"].items():
+        got = C.conv2d_cache_lookup(str(wp), None, C.shape(0, 0, int(f), int(f)))[0].tuple()
+        assert got == tuple(cfg)
+    monkeypatch.setenv("CONV2D_WINNERS", str(wp))
+    b = C.Batch(shapes)
+    used = {x["filter"][0]: tuple(x["config"]) for x in b.info["groups"]}
+    for f, cfg in r["assignment"].items():
+        assert used[int(f)][:6] == tuple(cfg)[:6]   # the build may roll the row loop
+    _check_batch_matches_oracle(torch, b, shapes, 130)
+    b.close()
