@@ -530,6 +530,14 @@ def hotspot_benchmark(reps: int = 20, warmup: int = 3, steps: int = 60, rows: in
         }
         plan.close()
     res["tuned_vs_default"] = round(res["default"]["ms"] / res["plan"]["ms"], 3)
+    # Roofline of the tuned plan: algorithmic intensity steps x 14 FLOP over
+    # the launch's 12 bytes per cell, against min(non-packed FP32 FMA peak,
+    # intensity x HBM peak).
+    p = res["plan"]
+    intensity = HOTSPOT_FLOP_PER_CELL_STEP * steps / p["launches"] / HOTSPOT_BYTES_PER_CELL_LAUNCH
+    roof = min(PEAK_FP32_UNPACKED_TFLOPS, intensity * PEAK_HBM_GBS / 1e3)
+    res["roofline"] = {"flop_per_byte": round(intensity, 3), "roof_tflops": round(roof, 2),
+                       "achieved_tflops": round(p["gflops"] / 1e3, 2), "frac": round(p["gflops"] / 1e3 / roof, 3)}
     return res
 
 
