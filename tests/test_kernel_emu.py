@@ -199,12 +199,23 @@ def _check_hotspot(tmp_path, cfgs, grids):
         power.tofile(tmp_path / "power.f32")
         ref = oracle.hotspot_f64(temp, power, steps, *k)
         bound = 8 * max(steps, 1) * 2.0 ** -24 * (1.0 + abs(k[4]) + steps * k[0] * 1.0)
-        first = None
-        for cfg, exe in zip(cfgs, exes):
-            r = subprocess.run([exe, str(rows), str(cols), str(steps), *[repr(v) for v in k], str(tmp_path)],
+
+        def emulate(job):
+            # each configuration in a directory of its own, so that they run in parallel
+            i, exe = job
+            d = tmp_path / f"run{i}"
+            d.mkdir(exist_ok=True)
+            for name in ("temp.f32", "power.f32"):
+                (d / name).write_bytes((tmp_path / name).read_bytes())
+            r = subprocess.run([exe, str(rows), str(cols), str(steps), *[repr(v) for v in k], str(d)],
                                capture_output=True, text=True, env=env, timeout=300)
             assert r.returncode == 0, r.stderr[-3000:]
-            got = np.fromfile(tmp_path / "out.f32", np.float32).reshape(rows, cols)
+            return np.fromfile(d / "out.f32", np.float32).reshape(rows, cols)
+
+        with cf.ThreadPoolExecutor(4) as ex:
+            outs = list(ex.map(emulate, enumerate(exes)))
+        first = None
+        for cfg, got in zip(cfgs, outs):
             assert np.all(np.isfinite(got)), (cfg, rows, cols)
             assert np.max(np.abs(got - ref)) <= bound, (cfg, rows, cols, np.max(np.abs(got - ref)))
             if first is None:
