@@ -530,15 +530,18 @@ def hotspot_benchmark(reps: int = 20, warmup: int = 3, steps: int = 60, rows: in
         }
         plan.close()
     res["tuned_vs_default"] = round(res["default"]["ms"] / res["plan"]["ms"], 3)
-    # Roofline of the tuned plan: algorithmic intensity steps x 14 FLOP over
-    # the launch's 12 bytes per cell, against min(non-packed FP32 FMA peak,
-    # intensity x HBM peak).
-    p = res["plan"]
-    intensity = HOTSPOT_FLOP_PER_CELL_STEP * steps / p["launches"] / HOTSPOT_BYTES_PER_CELL_LAUNCH
-    roof = min(PEAK_FP32_UNPACKED_TFLOPS, intensity * PEAK_HBM_GBS / 1e3)
-    res["roofline"] = {"flop_per_byte": round(intensity, 3), "roof_tflops": round(roof, 2),
-                       "achieved_tflops": round(p["gflops"] / 1e3, 2), "frac": round(p["gflops"] / 1e3 / roof, 3)}
+    res["roofline"] = hotspot_roofline(res["plan"]["gflops"], steps, res["plan"]["launches"])
     return res
+
+
+def hotspot_roofline(gflops: float, steps: int, launches: int) -> dict:
+    """Roofline of a hotspot run: algorithmic intensity steps x 14 FLOP over
+    the 12 bytes per cell that each of its launches moves, against
+    min(non-packed FP32 FMA peak, intensity x HBM peak)."""
+    intensity = HOTSPOT_FLOP_PER_CELL_STEP * steps / launches / HOTSPOT_BYTES_PER_CELL_LAUNCH
+    roof = min(PEAK_FP32_UNPACKED_TFLOPS, intensity * PEAK_HBM_GBS / 1e3)
+    return {"flop_per_byte": round(intensity, 3), "roof_tflops": round(roof, 2),
+            "achieved_tflops": round(gflops / 1e3, 2), "frac": round(gflops / 1e3 / roof, 3)}
 
 
 def calibration_copy(mib: int, reps: int = 3) -> dict:
