@@ -248,3 +248,40 @@ def test_reference_helpers_check_shapes_on_the_host():
     with pytest.raises(ValueError, match="float32"):
         C.reference(inp, f.double())
     torch.cuda.synchronize()
+
+
+def test_grid_too_wide_for_region_offsets():
+    """A grid so wide (9 x (2^27 + 1000) cells, 4.8 GB per array) that the
+    rows of a region span 2^31 bytes or more: every region, interior ones
+    included, takes the clamped 64-bit path. Three steps in two
+    configurations (one step and two steps per launch); windows at the left
+    edge, in the middle and at the right edge are compared with the FP64
+    oracle run on each window widened by steps + 1 columns, so that the
+    window's own borders, where the oracle would apply the grid-edge rule,
+    do not reach the compared cells."""
+    torch = torch_cuda()
+    rows, cols, steps = 9, (1 << 27) + 1000, 3
+    n = rows * cols
+    st = torch.cuda.current_stream().cuda_stream
+    temp = torch.empty((rows, cols), dtype=torch.float32, device="cuda")
+    power = torch.empty((rows, cols), dtype=torch.float32, device="cuda")
+    C.conv2d_fill_uniform(temp.data_ptr(), n, 71, 0, st)
+    C.conv2d_fill_uniform(power.data_ptr(), n, 72, 0, st)
+    m, w = steps + 1, 300
+    for cfg in [(16, 4, 1, 1, 1, 1, 1), (16, 4, 1, 2, 2, 0, 1)]:
+        plan = C.Hotspot(rows, cols, cfg)
+        say(f"hotspot {rows}x{cols} config {cfg}")
+        out = plan(temp, power, steps, STRESS)
+        torch.cuda.synchronize()
+        for c0 in (0, cols // 2 - w // 2, cols - w):
+            lo, hi = max(0, c0 - m), min(cols, c0 + w + m)
+            t = temp[:, lo:hi].cpu().numpy()
+            p = power[:, lo:hi].cpu().numpy()
+            ref = oracle.hotspot_f64(t, p, steps, *STRESS)[:, c0 - lo:c0 - lo + w]
+            got = out[:, c0:c0 + w].cpu().numpy()
+            assert np.all(np.isfinite(got)), (cfg, c0)
+            err = float(np.max(np.abs(got - ref)))
+            assert err <= bound(t, p, steps, STRESS), (cfg, c0, err)
+        del out
+        plan.close()
+    torch.cuda.empty_cache()
