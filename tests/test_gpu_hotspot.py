@@ -284,4 +284,9 @@ def test_grid_too_wide_for_region_offsets():
             assert err <= bound(t, p, steps, STRESS), (cfg, c0, err)
         del out
         plan.close()
-    torch.cuda.empty_cache()
+        del plan                                    # and its 4.8 GB work grid
+    del temp, power
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()                        # the next tests measure free device memory

@@ -152,7 +152,9 @@ def test_kept_output_allocation_failure_is_reported():
     needs) makes conv2d_serve return CONV2D_ENOMEM instead of waiting for
     memory that retiring requests cannot free; the outputs it had allocated
     are released (the free memory afterwards is what it was before)."""
+    import gc
     torch = torch_cuda()
+    gc.collect()                     # tensors of earlier tests still waiting for collection
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     free0, _ = torch.cuda.mem_get_info()
