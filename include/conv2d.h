@@ -322,7 +322,8 @@ int conv2d_batch_tune(int n, const conv2d_shape *shapes, const conv2d_batch_tune
                       conv2d_batch_tune_result *res);
 
 /* Compiles the batched kernel of a configuration (filter read through its
- * pointer, scalar loads and stores) for gfx950 with hiprtc, no GPU needed.
+ * pointer, one-dword input loads, 4-wide output stores at any dword-aligned
+ * row position) for gfx950 with hiprtc, no GPU needed.
  * Only s.filt_h and s.filt_w matter.
  * Source: Section 3 (compilation of each configuration). */
 int conv2d_compile_batch(conv2d_shape s, const conv2d_config *cfg, char *path_out, int path_cap);

@@ -189,11 +189,19 @@ conv2d_config batch_config_for(const DeviceInfo& dev, int fh, int fw, int bucket
     return lookup_batch_config(dev, winners_path_or_default(nullptr), fh, fw, bucket, fallback_bucket);
 }
 
+// Vector widths of the batched kernel. It loads its input one dword per lane
+// and load (rows of any alignment) and stores its outputs four dwords at a
+// time: a gfx9-family store of several dwords needs only dword alignment in
+// the alignment mode the ROCm driver sets, and a 4-wide store is issued only
+// where all four outputs lie inside the row. (A 4-wide load at the end of a
+// caller's input could reach up to 12 bytes past it; the loads stay one
+// dword wide.)
+static constexpr int kBatchVin = 1, kBatchVout = 4;
+
 int batch_module(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m)
 {
-    // The batched kernel stores with scalar writes (any row alignment); with
-    // a fully unrolled row loop that can spill, and the rolled loop is used.
-    return build_module(conv2d_shape{4096, 4096, fh, fw}, cfg, 1, 1, dev.arch, true, true, m);
+    // With a fully unrolled row loop that can spill, the rolled loop is used.
+    return build_module(conv2d_shape{4096, 4096, fh, fw}, cfg, kBatchVin, kBatchVout, dev.arch, true, true, m);
 }
 
 int launch_batch_kernel(const Module& m, const conv2d_config& cfg, int grid, const void* d_desc,
@@ -408,7 +416,7 @@ extern "C" int conv2d_compile_batch(conv2d_shape s, const conv2d_config* cfg, ch
     int rc = conv2d_config_check(s, &c, 0);
     if (rc) return rc;
     std::string path;
-    rc = compile_direct(s, c, 1, 1, env_str("CONV2D_ARCH", "gfx950"), nullptr, &path, true);
+    rc = compile_direct(s, c, kBatchVin, kBatchVout, env_str("CONV2D_ARCH", "gfx950"), nullptr, &path, true);
     if (rc) return rc;
     if (path_out && path_cap > 0) {
         std::strncpy(path_out, path.c_str(), (size_t)path_cap - 1);

@@ -22,7 +22,11 @@
 //   CONV_UNROLL        unroll of the input-row loop (0 = full)
 //   CONV_FH, CONV_FW   filter size
 //   CONV_VIN           input vector width 1/2/4 (row pitch and base aligned)
-//   CONV_VOUT          output vector width 1/2/4 (row pitch and base aligned)
+//   CONV_VOUT          output vector width 1/2/4: row pitch and base aligned
+//                      in a single-image kernel; the batched kernel uses 4
+//                      with rows of any alignment (a store of several dwords
+//                      needs only dword alignment on gfx9-family GPUs in the
+//                      alignment mode the ROCm driver sets)
 //   CONV_NAME          kernel symbol (one per configuration, so that profiles
 //                      tell configurations apart); default conv2d_direct
 //   CONV_BATCH         1: build the batched kernel (many images of

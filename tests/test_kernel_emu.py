@@ -115,7 +115,7 @@ BATCH_CONFIGS = [(16, 1, 1, 1, 0, 0, 1), (64, 1, 4, 4, 1, 0, 0), (32, 4, 2, 8, 0
 
 def build_batch(cfg, fh, fw):
     bx, by, tx, ty, lds, fc, un = cfg
-    defs = dict(BX=bx, BY=by, TX=tx, TY=ty, USE_LDS=lds, FCONST=0, UNROLL=un, FH=fh, FW=fw, VIN=1, VOUT=1, BATCH=1)
+    defs = dict(BX=bx, BY=by, TX=tx, TY=ty, USE_LDS=lds, FCONST=0, UNROLL=un, FH=fh, FW=fw, VIN=1, VOUT=4, BATCH=1)
     src = open(KERNEL).read() + open(os.path.join(EMU, "emu_batch.cpp")).read() + \
         open(os.path.join(EMU, "hip_emu.h")).read()
     key = hashlib.sha1((src + repr(sorted(defs.items()))).encode()).hexdigest()[:16]
@@ -132,11 +132,12 @@ def build_batch(cfg, fh, fw):
 
 @pytest.mark.parametrize("fh,fw", [(3, 3), (5, 2)])
 def test_emulated_batch_kernel_exact(fh, fw, tmp_path):
-    """The batched kernel over uneven images on grids smaller than its tile
+    """The batched kernel, built as the library builds it (4-wide stores at
+    any dword boundary), over uneven images on grids smaller than its tile
     count (each workgroup striding over several tiles): every output of every
     image written once and exact, for grids that are and are not multiples
-    of 8."""
-    sizes = [(37, 45), (5, 130), (64, 64), (1, 1), (19, 7)]
+    of 8, with rows of every width mod 4."""
+    sizes = [(37, 45), (5, 130), (64, 64), (1, 1), (19, 7), (9, 71)]
     probs = []
     for k, (H, W) in enumerate(sizes):
         inp, f = datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=100 + k, seed_f=200 + k)
