@@ -120,7 +120,11 @@ int conv2d_config_check(conv2d_shape s, const conv2d_config *cfg, int lds_limit)
 int conv2d_space(conv2d_shape s, int unroll, int lds_limit, conv2d_config *out, int cap);
 
 /* Compiles one configuration for gfx950 with hiprtc into the code-object
- * cache (no GPU needed). vec_in/vec_out are the alignment classes 1, 2 or 4.
+ * cache (no GPU needed). vec_in/vec_out are the load and store vector widths
+ * 1, 2 or 4: a plan builds with vec_in = the widest of 4, 2, 1 dividing the
+ * input row pitch (1 for a misaligned input base) and vec_out = 4 for rows
+ * of any width (1 with vec_in = 1 for a misaligned base), since a store of
+ * several dwords needs only dword alignment on gfx950.
  * Writes the cache file path to path_out (if non-NULL, cap bytes).
  * Returns CONV2D_OK or CONV2D_ECOMPILE (log in last_error).
  * Source: Section 3 (each configuration is compiled before it is benchmarked). */

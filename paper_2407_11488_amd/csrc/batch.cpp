@@ -189,14 +189,10 @@ conv2d_config batch_config_for(const DeviceInfo& dev, int fh, int fw, int bucket
     return lookup_batch_config(dev, winners_path_or_default(nullptr), fh, fw, bucket, fallback_bucket);
 }
 
-// Vector widths of the batched kernel. It loads its input one dword per lane
-// and load (rows of any alignment) and stores its outputs four dwords at a
-// time: a gfx9-family store of several dwords needs only dword alignment in
-// the alignment mode the ROCm driver sets, and a 4-wide store is issued only
-// where all four outputs lie inside the row. (A 4-wide load at the end of a
-// caller's input could reach up to 12 bytes past it; the loads stay one
-// dword wide.)
-static constexpr int kBatchVin = 1, kBatchVout = 4;
+// Vector widths of the batched kernel, whose problems' rows have every
+// alignment: one-dword loads (a 4-wide load at the end of a caller's input
+// could reach up to 12 bytes past it) and the 4-wide stores of every build.
+static constexpr int kBatchVin = 1, kBatchVout = kOutVec;
 
 int batch_module(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m)
 {

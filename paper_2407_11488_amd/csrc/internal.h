@@ -115,7 +115,15 @@ Geometry geometry(int out_h, int out_w, const conv2d_config& c);
 // Largest number of output rows per launch so that the input band stays below
 // 2^31 bytes (buffer offsets are 32-bit).
 int band_rows(const conv2d_shape& s);
+// Input vector width for rows of `elems_per_row` floats: 4, 2 or 1, the
+// widest that divides the row pitch (a vector load never crosses a row's
+// aligned vectors, nor the end of the caller's input).
 int vec_class(long long elems_per_row);
+// Output vector width of every build, for rows of any width: a thread's
+// outputs are stored four dwords at a time wherever all four lie inside the
+// row. A gfx9-family store of several dwords needs only dword alignment in
+// the alignment mode the ROCm driver sets.
+constexpr int kOutVec = 4;
 // Launches the direct kernel of `m` over the whole shape (in bands) on stream.
 int launch_direct(const Module& m, const conv2d_shape& s, const conv2d_config& c,
                   const float* d_in, const float* d_f, float* d_out, hipStream_t stream);

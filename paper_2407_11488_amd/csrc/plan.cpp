@@ -116,7 +116,7 @@ struct conv2d_plan_s {
     conv2d_shape shape{};
     conv2d_config cfg{};
     int source = 0;          // 0 default, 1 tuned, 2 forced/given, 3 tuned on an older kernel
-    int vin = 1, vout = 1;   // alignment classes of the main module
+    int vin = 1, vout = 1;   // vector widths of the main module
     Module main;
     Module unaligned;        // vin = vout = 1, compiled on first misaligned call
     std::mutex mu;
@@ -270,7 +270,7 @@ extern "C" int conv2d_plan(conv2d_plan_t* plan, conv2d_shape s, const conv2d_con
     rc = conv2d_config_check(s, &p->cfg, dev.lds_limit);
     if (rc) return rc;
     p->vin = vec_class((long long)s.out_w + s.filt_w - 1);
-    p->vout = vec_class(s.out_w);
+    p->vout = kOutVec;
     rc = build_module(p.get(), p->vin, p->vout, &p->main, true);
     if (rc) return rc;
     *plan = p.release();
@@ -318,7 +318,7 @@ extern "C" int conv2d_run(conv2d_plan_t plan, const float* d_in, const float* d_
 
     const Module* m = &plan->main;
     const bool aligned = reinterpret_cast<uintptr_t>(d_in) % (4u * plan->vin) == 0 &&
-                         reinterpret_cast<uintptr_t>(d_out) % (4u * plan->vout) == 0;
+                         reinterpret_cast<uintptr_t>(d_out) % 4u == 0;   // stores need dword alignment
     if (!aligned) {
         std::lock_guard<std::mutex> lk(plan->mu);
         if (!plan->unaligned.fn) {

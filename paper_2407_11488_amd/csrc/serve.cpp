@@ -433,7 +433,7 @@ private:
     // ---------------------------------------------------------------- serial plain
     int direct_module(const conv2d_shape& s, conv2d_config* cfg, const Module** m)
     {
-        const int vin = vec_class((long long)s.out_w + s.filt_w - 1), vout = vec_class(s.out_w);
+        const int vin = vec_class((long long)s.out_w + s.filt_w - 1), vout = kOutVec;
         const auto key = std::make_tuple(s.filt_h, s.filt_w, vin, vout);
         auto fit = direct_cfg_.find({s.filt_h, s.filt_w});
         if (fit == direct_cfg_.end()) {

@@ -237,7 +237,7 @@ public:
         n_in_ = ((size_t)s_.out_h + s_.filt_h - 1) * P_;
         n_out_ = (size_t)s_.out_h * s_.out_w;
         vin_ = vec_class((long long)P_);
-        vout_ = vec_class(s_.out_w);
+        vout_ = kOutVec;
         CONV2D_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
         CONV2D_HIP(hipEventCreate(&e0_));
         CONV2D_HIP(hipEventCreate(&e1_));

@@ -126,14 +126,9 @@ inline emu_u32x4 __builtin_amdgcn_raw_buffer_load_b128(__amdgpu_buffer_rsrc_t r,
 template <class T>
 inline void emu_nontemporal_store(T v, T* p)
 {
-    // A gfx9-family store of several dwords needs dword alignment. The
-    // single-image kernel is built for rows aligned to its vector width and
-    // is held to that; the batched kernel stores at any dword boundary.
-#if defined(CONV_BATCH) && CONV_BATCH
+    // A gfx9-family store of several dwords needs only dword alignment: the
+    // kernels store four-wide at any dword boundary of a row.
     assert(reinterpret_cast<uintptr_t>(p) % 4 == 0);
-#else
-    assert(reinterpret_cast<uintptr_t>(p) % sizeof(T) == 0);
-#endif
     std::memcpy(static_cast<void*>(p), &v, sizeof(T));
 }
 #define __builtin_nontemporal_store(v, p) emu_nontemporal_store(v, p)

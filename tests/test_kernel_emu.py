@@ -2,7 +2,8 @@
 thread, real barriers, bounds-checked buffer loads, AddressSanitizer and
 UBSan. Each configuration must equal the FP64 oracle bit for bit on integer
 data (exact in any order), write every output, and make no out-of-bounds
-access, on pitches of every alignment class. No GPU needed."""
+access, on input pitches of every alignment class, with the four-wide
+stores the library builds for rows of every width. No GPU needed."""
 import concurrent.futures as cf
 import hashlib
 import os
@@ -88,8 +89,8 @@ def binaries():
                 continue
             jobs.append(((H, W, fh, fw), cfg))
     with cf.ThreadPoolExecutor(os.cpu_count() or 4) as ex:
-        futs = {job: ex.submit(build, job[1], job[0][2], job[0][3], vec_class(job[0][1] + job[0][3] - 1),
-                               vec_class(job[0][1])) for job in jobs}
+        futs = {job: ex.submit(build, job[1], job[0][2], job[0][3], vec_class(job[0][1] + job[0][3] - 1), 4)
+                for job in jobs}
         return {job: f.result() for job, f in futs.items()}
 
 
