@@ -207,6 +207,26 @@ def test_full_size_integer_data_bitwise():
     assert np.array_equal(got, ref), int(np.count_nonzero(got != ref))
 
 
+@pytest.mark.parametrize("H,W,fsize", [(4093, 4095, 17), (4095, 4093, 3), (4094, 4093, 9), (2049, 4094, 5)])
+def test_full_size_odd_widths_integer_bitwise(H, W, fsize):
+    """Outputs whose rows are 1, 2 or 3 floats past a multiple of 4, so that
+    the plan's four-dword stores start at every dword position of a 16-byte
+    line, in the configuration the plan picks (the filter's 4096x4096
+    winner): with integer data in [-4, 4] every partial sum is an integer
+    below 2^24 and the whole output equals the FP64 oracle bit for bit."""
+    torch = torch_cuda()
+    inp, f = datagen.conv_problem(H, W, fsize, fsize, kind="int", seed_in=91, seed_f=92)
+    plan = C.Plan(H, W, fsize, fsize)
+    say(f"odd width {H}x{W} f{fsize} with {plan.source} config {plan.config}")
+    out = plan(to_dev(inp), to_dev(f), out=nan_like(H, W))
+    torch.cuda.synchronize()
+    plan.close()
+    got = out.cpu().numpy().astype(np.float64)
+    del out
+    ref, _ = oracle.conv2d_f64(inp, f, with_abs=False)
+    assert np.array_equal(got, ref), int(np.count_nonzero(got != ref))
+
+
 def test_input_above_2gib_runs_in_bands():
     """An input above 2 GiB (output 24000 x 24000, 3 x 3 filter: 2.3 GB) runs
     as several launches over horizontal bands (32-bit buffer offsets): sampled
