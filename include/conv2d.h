@@ -121,10 +121,9 @@ int conv2d_space(conv2d_shape s, int unroll, int lds_limit, conv2d_config *out, 
 
 /* Compiles one configuration for gfx950 with hiprtc into the code-object
  * cache (no GPU needed). vec_in/vec_out are the load and store vector widths
- * 1, 2 or 4: a plan builds with vec_in = the widest of 4, 2, 1 dividing the
- * input row pitch (1 for a misaligned input base) and vec_out = 4 for rows
- * of any width (1 with vec_in = 1 for a misaligned base), since a store of
- * several dwords needs only dword alignment on gfx950.
+ * 1, 2 or 4; plans, the tuner and the batched path build with 4 and 4 for
+ * rows of any width (an access of several dwords needs only dword alignment
+ * on gfx950, and each dword of a buffer load is range-checked).
  * Writes the cache file path to path_out (if non-NULL, cap bytes).
  * Returns CONV2D_OK or CONV2D_ECOMPILE (log in last_error).
  * Source: Section 3 (each configuration is compiled before it is benchmarked). */
@@ -186,9 +185,8 @@ int conv2d_plan_config(conv2d_plan_t plan, conv2d_config *cfg, int *tuned);
  * constant array: such a plan must not run concurrently on two streams. The
  * call may be recorded by stream capture into a graph (a copy node, when the
  * filter goes to constant memory, then the kernel node); replays read the
- * buffers' current contents. Capture a call whose pointers are aligned as the
- * plan's first run will be, or run it once first: the first misaligned call
- * compiles a second module.
+ * buffers' current contents. Pointers need 4-byte alignment only (one module
+ * serves every alignment).
  * Source: Section 5 (the convolution benchmark kernel); Table 1 (read_only,
  * use_shmem, tile and block sizes select the variant enqueued). */
 int conv2d_run(conv2d_plan_t plan, const float *d_in, const float *d_filter, float *d_out,
@@ -326,8 +324,8 @@ int conv2d_batch_tune(int n, const conv2d_shape *shapes, const conv2d_batch_tune
                       conv2d_batch_tune_result *res);
 
 /* Compiles the batched kernel of a configuration (filter read through its
- * pointer, one-dword input loads, 4-wide output stores at any dword-aligned
- * row position) for gfx950 with hiprtc, no GPU needed.
+ * pointer, 4-wide loads and stores at any dword position) for gfx950 with
+ * hiprtc, no GPU needed.
  * Only s.filt_h and s.filt_w matter.
  * Source: Section 3 (compilation of each configuration). */
 int conv2d_compile_batch(conv2d_shape s, const conv2d_config *cfg, char *path_out, int path_cap);

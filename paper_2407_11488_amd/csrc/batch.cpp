@@ -189,10 +189,9 @@ conv2d_config batch_config_for(const DeviceInfo& dev, int fh, int fw, int bucket
     return lookup_batch_config(dev, winners_path_or_default(nullptr), fh, fw, bucket, fallback_bucket);
 }
 
-// Vector widths of the batched kernel, whose problems' rows have every
-// alignment: one-dword loads (a 4-wide load at the end of a caller's input
-// could reach up to 12 bytes past it) and the 4-wide stores of every build.
-static constexpr int kBatchVin = 1, kBatchVout = kOutVec;
+// The batched kernel's problems have rows of every alignment; it takes the
+// 4-wide loads and stores of every build.
+static constexpr int kBatchVin = kVec, kBatchVout = kVec;
 
 int batch_module(const DeviceInfo& dev, int fh, int fw, conv2d_config* cfg, Module* m)
 {

@@ -21,12 +21,14 @@
 //                      0: filter read through a const __restrict__ pointer
 //   CONV_UNROLL        unroll of the input-row loop (0 = full)
 //   CONV_FH, CONV_FW   filter size
-//   CONV_VIN           input vector width 1/2/4 (row pitch and base aligned)
-//   CONV_VOUT          output vector width 1/2/4: row pitch and base aligned
-//                      in a single-image kernel; the batched kernel uses 4
-//                      with rows of any alignment (a store of several dwords
-//                      needs only dword alignment on gfx9-family GPUs in the
-//                      alignment mode the ROCm driver sets)
+//   CONV_VIN           input vector width 1/2/4
+//   CONV_VOUT          output vector width 1/2/4
+//                      The library builds every kernel with 4 and 4, for rows
+//                      of any width: a gfx9-family access of several dwords
+//                      needs only dword alignment in the alignment mode the
+//                      ROCm driver sets, and a raw buffer load checks each
+//                      dword against the buffer size (a vector that straddles
+//                      the end of the input reads zeros past it).
 //   CONV_NAME          kernel symbol (one per configuration, so that profiles
 //                      tell configurations apart); default conv2d_direct
 //   CONV_BATCH         1: build the batched kernel (many images of
@@ -39,7 +41,7 @@
 //    it (TY*TX*FW FMAs per window in the steady state). Filter taps are wave
 //    uniform and are read with scalar loads, so each FMA is
 //    v_fmac_f32 acc, s_tap, v_in.
-//  * Global reads use raw buffer loads: an out-of-range offset returns 0
+//  * Global reads use raw buffer loads: an out-of-range dword reads 0
 //    instead of faulting, so edge tiles need no clamping; outputs outside the
 //    image are simply not stored.
 //  * Workgroup ids are remapped so that each of the 8 XCDs (dispatched
@@ -75,9 +77,9 @@ struct Geo {
     static constexpr int NT = BX * BY;
     static constexpr int WIN = TX + FW - 1;      // input values a thread's row window needs
     static constexpr int NROWS = TY + FH - 1;    // input rows a thread walks
-    // Vector width of a thread's window loads. The window starts at a
-    // multiple of TX: from global memory it is aligned to min(gcd(TX, 4), VIN)
-    // elements, from LDS (pitch a multiple of 4) to gcd(TX, 4). The register
+    // Vector width of a thread's window loads: min(gcd(TX, 4), VIN) from
+    // global memory, gcd(TX, 4) from LDS (pitch a multiple of 4, the window
+    // starting at a multiple of TX, so LDS reads stay aligned). The register
     // window is padded to a whole number of those vectors.
     static constexpr int WVEC = LDS ? gcd4(TX) : min_(gcd4(TX), VIN);
     static constexpr int WIN_PAD = ((WIN + WVEC - 1) / WVEC) * WVEC;

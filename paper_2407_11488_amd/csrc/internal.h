@@ -115,15 +115,14 @@ Geometry geometry(int out_h, int out_w, const conv2d_config& c);
 // Largest number of output rows per launch so that the input band stays below
 // 2^31 bytes (buffer offsets are 32-bit).
 int band_rows(const conv2d_shape& s);
-// Input vector width for rows of `elems_per_row` floats: 4, 2 or 1, the
-// widest that divides the row pitch (a vector load never crosses a row's
-// aligned vectors, nor the end of the caller's input).
-int vec_class(long long elems_per_row);
-// Output vector width of every build, for rows of any width: a thread's
-// outputs are stored four dwords at a time wherever all four lie inside the
-// row. A gfx9-family store of several dwords needs only dword alignment in
-// the alignment mode the ROCm driver sets.
-constexpr int kOutVec = 4;
+// Load and store vector width of every build of the direct kernel, for rows
+// of any width and pointers at any dword boundary. A gfx9-family memory
+// instruction of several dwords needs only dword alignment in the alignment
+// mode the ROCm driver sets. A raw buffer load checks each dword against the
+// buffer's size: a 4-wide load that straddles the end of the input returns
+// zeros for the dwords past it, like a load wholly past it. A 4-wide store is
+// issued only where all four outputs lie inside the row.
+constexpr int kVec = 4;
 // Launches the direct kernel of `m` over the whole shape (in bands) on stream.
 int launch_direct(const Module& m, const conv2d_shape& s, const conv2d_config& c,
                   const float* d_in, const float* d_f, float* d_out, hipStream_t stream);

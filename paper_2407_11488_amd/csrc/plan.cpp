@@ -77,11 +77,6 @@ int band_rows(const conv2d_shape& s)
     return (int)std::min<long long>(rows, s.out_h);
 }
 
-int vec_class(long long elems)
-{
-    return (elems % 4 == 0) ? 4 : (elems % 2 == 0) ? 2 : 1;
-}
-
 int launch_direct(const Module& m, const conv2d_shape& s, const conv2d_config& c, const float* d_in,
                   const float* d_f, float* d_out, hipStream_t stream)
 {
@@ -116,10 +111,7 @@ struct conv2d_plan_s {
     conv2d_shape shape{};
     conv2d_config cfg{};
     int source = 0;          // 0 default, 1 tuned, 2 forced/given, 3 tuned on an older kernel
-    int vin = 1, vout = 1;   // vector widths of the main module
     Module main;
-    Module unaligned;        // vin = vout = 1, compiled on first misaligned call
-    std::mutex mu;
 };
 
 // ---------------------------------------------------------------- host-only API
@@ -213,15 +205,15 @@ extern "C" int conv2d_geometry(conv2d_shape s, const conv2d_config* cfg, int* ti
 
 // ---------------------------------------------------------------- plan / run
 
-// Builds the plan's module for an alignment class. A configuration the
-// library chose (tuned or default) falls back to the rolled row loop if this
-// alignment class makes it spill; a given or forced one is built as asked.
-// Only the unroll can change, which does not affect the launch geometry.
-static int build_module(conv2d_plan_s* p, int vin, int vout, Module* m, bool is_main)
+// Builds the plan's module. A configuration the library chose (tuned or
+// default) falls back to the rolled row loop if it spills; a given or forced
+// one is built as asked. Only the unroll can change, which does not affect
+// the launch geometry.
+static int build_module(conv2d_plan_s* p)
 {
     conv2d_config c = p->cfg;
-    int rc = build_module(p->shape, &c, vin, vout, p->arch, false, p->source != 2, m);
-    if (rc == CONV2D_OK && is_main) p->cfg = c;
+    int rc = build_module(p->shape, &c, kVec, kVec, p->arch, false, p->source != 2, &p->main);
+    if (rc == CONV2D_OK) p->cfg = c;
     return rc;
 }
 
@@ -269,9 +261,7 @@ extern "C" int conv2d_plan(conv2d_plan_t* plan, conv2d_shape s, const conv2d_con
     }
     rc = conv2d_config_check(s, &p->cfg, dev.lds_limit);
     if (rc) return rc;
-    p->vin = vec_class((long long)s.out_w + s.filt_w - 1);
-    p->vout = kOutVec;
-    rc = build_module(p.get(), p->vin, p->vout, &p->main, true);
+    rc = build_module(p.get());
     if (rc) return rc;
     *plan = p.release();
     return CONV2D_OK;
@@ -316,17 +306,7 @@ extern "C" int conv2d_run(conv2d_plan_t plan, const float* d_in, const float* d_
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
 
-    const Module* m = &plan->main;
-    const bool aligned = reinterpret_cast<uintptr_t>(d_in) % (4u * plan->vin) == 0 &&
-                         reinterpret_cast<uintptr_t>(d_out) % 4u == 0;   // stores need dword alignment
-    if (!aligned) {
-        std::lock_guard<std::mutex> lk(plan->mu);
-        if (!plan->unaligned.fn) {
-            rc = build_module(plan, 1, 1, &plan->unaligned, false);
-            if (rc) return rc;
-        }
-        m = &plan->unaligned;
-    }
+    const Module* m = &plan->main;   // pointers are dword aligned (check_buffers)
     if (plan->cfg.filter_in_const) {
         if (!m->const_filter || m->const_bytes < sizeof(float) * plan->shape.filt_h * plan->shape.filt_w)
             return fail(CONV2D_EHIP, "module has no conv_filter symbol of the filter's size");
@@ -341,7 +321,6 @@ extern "C" void conv2d_destroy(conv2d_plan_t plan)
 {
     if (!plan) return;
     unload_module(&plan->main);
-    unload_module(&plan->unaligned);
     delete plan;
 }
 

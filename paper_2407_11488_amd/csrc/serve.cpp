@@ -433,8 +433,7 @@ private:
     // ---------------------------------------------------------------- serial plain
     int direct_module(const conv2d_shape& s, conv2d_config* cfg, const Module** m)
     {
-        const int vin = vec_class((long long)s.out_w + s.filt_w - 1), vout = kOutVec;
-        const auto key = std::make_tuple(s.filt_h, s.filt_w, vin, vout);
+        const auto key = std::make_tuple(s.filt_h, s.filt_w, kVec, kVec);
         auto fit = direct_cfg_.find({s.filt_h, s.filt_w});
         if (fit == direct_cfg_.end()) {
             std::string wp = env_str("CONV2D_WINNERS");
@@ -452,7 +451,7 @@ private:
         if (it == direct_.end()) {
             conv2d_config built = *cfg;  // only the unroll may change, not the geometry
             Module mod;
-            int rc = build_module(s, &built, vin, vout, dev_.arch, false, true, &mod);
+            int rc = build_module(s, &built, kVec, kVec, dev_.arch, false, true, &mod);
             if (rc) return rc;
             it = direct_.emplace(key, mod).first;
         }

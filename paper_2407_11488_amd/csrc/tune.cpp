@@ -236,8 +236,7 @@ public:
         P_ = (size_t)s_.out_w + s_.filt_w - 1;
         n_in_ = ((size_t)s_.out_h + s_.filt_h - 1) * P_;
         n_out_ = (size_t)s_.out_h * s_.out_w;
-        vin_ = vec_class((long long)P_);
-        vout_ = kOutVec;
+        vin_ = vout_ = kVec;
         CONV2D_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
         CONV2D_HIP(hipEventCreate(&e0_));
         CONV2D_HIP(hipEventCreate(&e1_));

@@ -109,7 +109,7 @@ inline void __builtin_amdgcn_sched_barrier(int) {}
 
 inline emu_u32x2 __builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
 {
-    assert(soff == 0 && aux == 0 && (off & 7) == 0);
+    assert(soff == 0 && aux == 0 && (off & 3) == 0);  // any dword offset, as on gfx9
     uint32_t v[2];
     emu_buffer_read(r, off, 2, v);
     return emu_u32x2{v[0], v[1]};
@@ -117,7 +117,7 @@ inline emu_u32x2 __builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t r, 
 
 inline emu_u32x4 __builtin_amdgcn_raw_buffer_load_b128(__amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
 {
-    assert(soff == 0 && aux == 0 && (off & 15) == 0);
+    assert(soff == 0 && aux == 0 && (off & 3) == 0);  // any dword offset, as on gfx9
     uint32_t v[4];
     emu_buffer_read(r, off, 4, v);
     return emu_u32x4{v[0], v[1], v[2], v[3]};

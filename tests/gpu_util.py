@@ -52,12 +52,7 @@ def precompile(C, shape, cfgs, vin, vout, threads=16):
         list(ex.map(lambda c: C.conv2d_compile(shape, c, vin, vout), cfgs))
 
 
-def vec_class(n):
-    """Load vector width a plan builds with for input rows of n floats."""
-    return 4 if n % 4 == 0 else (2 if n % 2 == 0 else 1)
-
-
-OUT_VEC = 4   # store vector width of every plan (rows of any width)
+VEC = 4   # load and store vector width of every plan (rows of any width)
 
 
 def say(msg):

@@ -55,11 +55,11 @@ def test_plain_run_captured_and_replayed(cfg):
 def test_plan_shared_by_threads_on_their_own_streams():
     """One plan (filter through its pointer) used by four host threads at
     once, each on its own stream with its own buffers, twenty runs each, the
-    first call of each thread misaligned (the plan's second module is built
-    under its lock): every output equals a single-threaded run bit for bit."""
+    first call of each thread with pointers one float past a 16-byte
+    boundary: every output equals a single-threaded run bit for bit."""
     import threading
     torch = torch_cuda()
-    H, W, fh, fw = 200, 132, 7, 7   # input rows of 138 floats: the main module reads pairs
+    H, W, fh, fw = 200, 132, 7, 7   # input rows of 138 floats: 4-wide loads cross 16-byte boundaries
     plan = C.Plan(H, W, fh, fw, config=(32, 4, 4, 2, 0, 0, 1))
     data = [datagen.conv_problem(H, W, fh, fw, seed_in=80 + k, seed_f=90 + k) for k in range(4)]
     want = []
@@ -78,11 +78,11 @@ def test_plan_shared_by_threads_on_their_own_streams():
             big_in[1:] = di.reshape(-1)
             big_out = torch.full((H * W + 1,), float("nan"), device="cuda")
             torch.cuda.synchronize()
-            # first call misaligned by one float, then aligned calls
+            # first call one float past a 16-byte boundary, then aligned calls
             C.conv2d_run(plan.handle, big_in.data_ptr() + 4, df.data_ptr(), big_out.data_ptr() + 4, s.cuda_stream)
             s.synchronize()
             if not np.array_equal(big_out[1:].cpu().numpy().view(np.uint32), want[k].reshape(-1).view(np.uint32)):
-                errors.append((k, "misaligned"))
+                errors.append((k, "offset by one float"))
             out = torch.full((H, W), float("nan"), device="cuda")
             torch.cuda.synchronize()                   # the fill runs on the default stream
             for _ in range(20):

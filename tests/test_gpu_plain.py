@@ -5,7 +5,7 @@ import pytest
 
 import datagen
 import oracle
-from tests.gpu_util import OUT_VEC, TOL, nan_like, precompile, run_config, say, to_dev, torch_cuda, vec_class
+from tests.gpu_util import TOL, VEC, nan_like, precompile, run_config, say, to_dev, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -67,7 +67,7 @@ def test_whole_space_integer_data_bitwise():
     for c in illegal:
         with pytest.raises(C.Conv2dError):
             C.conv2d_plan(s, c)
-    precompile(C, s, cfgs, vec_class(W + fw - 1), OUT_VEC)
+    precompile(C, s, cfgs, VEC, VEC)
     inp, f = datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=8, seed_f=9)
     ref, _ = oracle.conv2d_f64(inp, f)
     di, df = to_dev(inp), to_dev(f)
@@ -98,7 +98,7 @@ def test_stratified_configs_uniform(fh, fw):
     H, W = 203, 317
     s = C.shape(H, W, fh, fw)
     cfgs = [c + (1,) for c in STRATIFIED if C.conv2d_config_check(s, c + (1,)) == 0]
-    precompile(C, s, cfgs, vec_class(W + fw - 1), OUT_VEC)
+    precompile(C, s, cfgs, VEC, VEC)
     inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=10 + fh, seed_f=20 + fw)
     di, df = to_dev(inp), to_dev(f)
     first = None
@@ -114,8 +114,9 @@ def test_stratified_configs_uniform(fh, fw):
 @pytest.mark.parametrize("cfg", [(64, 1, 8, 8, 0, 0, 1), (16, 16, 1, 1, 1, 1, 1), (64, 2, 4, 4, 1, 0, 2),
                                  (64, 1, 2, 4, 0, 1, 0), (32, 4, 8, 2, 0, 0, 4)])
 def test_unroll_and_alignment_variants(cfg):
-    """Unroll factors, and misaligned input/output pointers (views offset by one
-    float), which take the unaligned-vector module."""
+    """Unroll factors, and input/output pointers one float past a 16-byte
+    boundary (views offset by one float), which the plan's one module (4-wide
+    loads and stores at any dword offset) takes as they are."""
     torch = torch_cuda()
     H, W, fh, fw = 129, 260, 17, 17
     inp, f = datagen.conv_problem(H, W, fh, fw, seed_in=31, seed_f=32)
@@ -148,7 +149,7 @@ def test_largest_filters_integer_bitwise(fh, fw):
     cfgs = [c for c in [(64, 1, 1, 1, 0, 0, 1), (16, 16, 2, 2, 1, 0, 1), (32, 4, 4, 2, 0, 1, 1),
                         (128, 2, 2, 4, 1, 1, 1)] if C.conv2d_config_check(s, c) == 0]
     assert len(cfgs) >= 3
-    precompile(C, s, cfgs, vec_class(W + fw - 1), OUT_VEC)
+    precompile(C, s, cfgs, VEC, VEC)
     inp, f = datagen.conv_problem(H, W, fh, fw, kind="int", seed_in=41, seed_f=42)
     ref, _ = oracle.conv2d_f64(inp, f)
     di, df = to_dev(inp), to_dev(f)
@@ -300,7 +301,7 @@ def test_errors_are_reported_not_faulted():
             C.conv2d_run(plan, inp.data_ptr(), f.data_ptr(), 0, st)
         assert e.value.status == C.CONV2D_EINVAL
         with pytest.raises(C.Conv2dError):
-            C.conv2d_run(plan, inp.data_ptr() + 2, f.data_ptr(), out.data_ptr(), st)  # misaligned
+            C.conv2d_run(plan, inp.data_ptr() + 2, f.data_ptr(), out.data_ptr(), st)  # not 4-byte aligned
         host = np.zeros(64 * 64, np.float32)
         with pytest.raises(C.Conv2dError):
             C.conv2d_run(plan, inp.data_ptr(), f.data_ptr(), host.ctypes.data, st)

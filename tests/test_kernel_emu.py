@@ -2,8 +2,9 @@
 thread, real barriers, bounds-checked buffer loads, AddressSanitizer and
 UBSan. Each configuration must equal the FP64 oracle bit for bit on integer
 data (exact in any order), write every output, and make no out-of-bounds
-access, on input pitches of every alignment class, with the four-wide
-stores the library builds for rows of every width. No GPU needed."""
+access, on input pitches and output widths of every residue mod 4, with
+the four-wide loads and stores the library builds for all of them (each
+dword of a buffer load range-checked, as on the GPU). No GPU needed."""
 import concurrent.futures as cf
 import hashlib
 import os
@@ -42,13 +43,10 @@ def sample_configs():
     return out
 
 
-# (H, W, fh, fw): odd pitch (vector width 1), pitch = 2 mod 4, pitch = 0 mod 4,
+# (H, W, fh, fw): input pitches 47, 38, 76, 8, 43 and 41 (3, 2, 0, 0, 3 and 1
+# mod 4), output widths 45, 36, 72, 5, 39 and 38 (1, 0, 0, 1, 3 and 2 mod 4),
 # and a shape smaller than one tile.
-SHAPES = [(21, 45, 5, 3), (13, 36, 3, 3), (9, 72, 7, 5), (3, 5, 2, 4)]
-
-
-def vec_class(n):
-    return 4 if n % 4 == 0 else (2 if n % 2 == 0 else 1)
+SHAPES = [(21, 45, 5, 3), (13, 36, 3, 3), (9, 72, 7, 5), (3, 5, 2, 4), (11, 39, 3, 5), (7, 38, 4, 4)]
 
 
 def build(cfg, fh, fw, vin, vout):
@@ -89,8 +87,7 @@ def binaries():
                 continue
             jobs.append(((H, W, fh, fw), cfg))
     with cf.ThreadPoolExecutor(os.cpu_count() or 4) as ex:
-        futs = {job: ex.submit(build, job[1], job[0][2], job[0][3], vec_class(job[0][1] + job[0][3] - 1), 4)
-                for job in jobs}
+        futs = {job: ex.submit(build, job[1], job[0][2], job[0][3], 4, 4) for job in jobs}
         return {job: f.result() for job, f in futs.items()}
 
 
@@ -116,7 +113,7 @@ BATCH_CONFIGS = [(16, 1, 1, 1, 0, 0, 1), (64, 1, 4, 4, 1, 0, 0), (32, 4, 2, 8, 0
 
 def build_batch(cfg, fh, fw):
     bx, by, tx, ty, lds, fc, un = cfg
-    defs = dict(BX=bx, BY=by, TX=tx, TY=ty, USE_LDS=lds, FCONST=0, UNROLL=un, FH=fh, FW=fw, VIN=1, VOUT=4, BATCH=1)
+    defs = dict(BX=bx, BY=by, TX=tx, TY=ty, USE_LDS=lds, FCONST=0, UNROLL=un, FH=fh, FW=fw, VIN=4, VOUT=4, BATCH=1)
     src = open(KERNEL).read() + open(os.path.join(EMU, "emu_batch.cpp")).read() + \
         open(os.path.join(EMU, "hip_emu.h")).read()
     key = hashlib.sha1((src + repr(sorted(defs.items()))).encode()).hexdigest()[:16]
@@ -133,8 +130,8 @@ def build_batch(cfg, fh, fw):
 
 @pytest.mark.parametrize("fh,fw", [(3, 3), (5, 2)])
 def test_emulated_batch_kernel_exact(fh, fw, tmp_path):
-    """The batched kernel, built as the library builds it (4-wide stores at
-    any dword boundary), over uneven images on grids smaller than its tile
+    """The batched kernel, built as the library builds it (4-wide loads and
+    stores at any dword boundary), over uneven images on grids smaller than its tile
     count (each workgroup striding over several tiles): every output of every
     image written once and exact, for grids that are and are not multiples
     of 8, with rows of every width mod 4."""
