@@ -84,6 +84,21 @@ def test_compiled_code_is_plain_fp32_fma_without_spills(cfg):
     assert n["private_segment_fixed_size"] == 0 and n["vgpr_spill_count"] == 0
 
 
+def test_batched_kernel_is_built_four_wide(tmp_path):
+    """The batched kernel is built with four-dword loads and stores (rows of
+    every alignment in one launch), as the compile log of a fresh process
+    records it."""
+    log = tmp_path / "compiles.log"
+    code = ("import paper_2407_11488_amd as C; "
+            "C.conv2d_compile_batch(C.shape(4096, 4096, 5, 5), (64, 4, 4, 4, 0, 0, 1))")
+    env = dict(os.environ, CONV2D_COMPILE_LOG=str(log))
+    subprocess.run(["python3", "-c", code], check=True, env=env, cwd=os.path.dirname(os.path.dirname(__file__)),
+                   timeout=300)
+    lines = [ln for ln in log.read_text().splitlines() if ln.startswith("conv2d_direct.hip")]
+    assert len(lines) == 1, lines
+    assert "-DCONV_VIN=4 -DCONV_VOUT=4 -DCONV_BATCH=1" in lines[0], lines[0]
+
+
 def test_batched_kernels_of_the_cached_choices_compile_without_spills():
     """The batched kernel of every configuration the batched path and the
     server take from the committed winners cache (whole-batch and size-bucket
