@@ -53,6 +53,8 @@
 #endif
 
 #define HS_NT (HS_BX * HS_BY)
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
 #define RH (HS_BY * HS_TY)   // region rows
 #define RW (HS_BX * HS_TX)   // region columns
 #define OH (RH - 2 * HS_TT)  // output tile rows
@@ -332,12 +334,36 @@ HS_NAME(const float* __restrict__ tin, const float* __restrict__ power, float* _
             const int R = R0 + a;
             if (R < HS_TT || R >= RH - HS_TT)
                 continue;
+            if constexpr (HS_TX % 2 == 0) {
+                // Two neighbouring outputs of the output tile go out as one
+                // two-dword store (it needs only dword alignment): half the
+                // store instructions, each writing whole 8-byte pairs.
 #pragma unroll
-            for (int b = 0; b < HS_TX; ++b) {
-                const int C = C0 + b;
-                if (C >= HS_TT && C < RW - HS_TT)
-                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v[a][b]), ro,
-                                                          (int)(voff + 4u * b), a * cols * 4, 0);
+                for (int b = 0; b < HS_TX; b += 2) {
+                    const int C = C0 + b;
+                    const bool in0 = C >= HS_TT && C < RW - HS_TT;
+                    const bool in1 = C + 1 >= HS_TT && C + 1 < RW - HS_TT;
+                    if (in0 && in1) {
+                        const u32x2 w = {__builtin_bit_cast(unsigned, v[a][b]),
+                                         __builtin_bit_cast(unsigned, v[a][b + 1])};
+                        __builtin_amdgcn_raw_buffer_store_b64(w, ro, (int)(voff + 4u * b), a * cols * 4, 0);
+                    } else {
+                        if (in0)
+                            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v[a][b]), ro,
+                                                                  (int)(voff + 4u * b), a * cols * 4, 0);
+                        if (in1)
+                            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v[a][b + 1]), ro,
+                                                                  (int)(voff + 4u * (b + 1)), a * cols * 4, 0);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < HS_TX; ++b) {
+                    const int C = C0 + b;
+                    if (C >= HS_TT && C < RW - HS_TT)
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v[a][b]), ro,
+                                                              (int)(voff + 4u * b), a * cols * 4, 0);
+                }
             }
         }
     }

@@ -105,6 +105,15 @@ inline void __builtin_amdgcn_raw_buffer_store_b32(unsigned v, __amdgpu_buffer_rs
         std::memcpy(const_cast<char*>(r.base) + o, &v, 4);  // ASan checks the allocation
 }
 
+// Each dword of a two-dword store is range-checked on its own.
+template <class V2>
+inline void __builtin_amdgcn_raw_buffer_store_b64(V2 v, __amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
+{
+    assert(soff >= 0 && aux == 0 && (off & 3) == 0);
+    __builtin_amdgcn_raw_buffer_store_b32(v[0], r, off, soff, aux);
+    __builtin_amdgcn_raw_buffer_store_b32(v[1], r, off + 4, soff, aux);
+}
+
 inline void __builtin_amdgcn_sched_barrier(int) {}
 
 inline emu_u32x2 __builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t r, int off, int soff, int aux)
